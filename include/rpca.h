@@ -1,0 +1,170 @@
+/*
+ * rpca.h - C ABI of the MI355X RPCA library (librpca_mi355x.so).
+ *
+ * The library decomposes a Casorati matrix M (pixels x frames) into a
+ * low-rank part L and a sparse part S by the inexact augmented-Lagrangian
+ * (ADMM) iteration of principal component pursuit:
+ *
+ *   minimise ||L||_* + lambda ||S||_1  subject to  L + S = M      (paper Eq. 2)
+ *
+ *   repeat  L = D_{1/mu}(M - S + Y/mu)       singular value thresholding (Eq. 4)
+ *           S = shrink_{lambda/mu}(M - L + Y/mu)                         (Eq. 5)
+ *           Y = Y + mu (M - L - S)                                       (Eq. 6)
+ *   until   ||M - L - S||_F < tol ||M||_F        (Sec. II-A, after Eq. 6)
+ *
+ * with S and Y starting at zero and mu fixed.  The singular value
+ * thresholding is computed through the n x n Gram matrix A^T A of
+ * A = M - S + Y/mu and its FP64 eigendecomposition on the GPU; the result is
+ * the same operator D_tau(A) (a spectral function of A).
+ *
+ * Layout of every matrix argument: m x n, column-major, leading dimension m.
+ * Element (p, t) - pixel p, frame t - is at offset p + t*m, so frame t is
+ * contiguous (each frame is one column of the Casorati matrix, Sec. II-A).
+ * A C-contiguous (n_frames, H, W) image stack is exactly this layout with
+ * m = H*W.
+ *
+ * Memory: M, L and S are DEVICE pointers allocated by the caller on the
+ * current HIP device.  M is read only.  L and S are fully overwritten and
+ * must not overlap M or each other.  The library allocates and owns its
+ * workspace (stream-ordered, from a cached pool; see rpca_footprint_bytes).
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  All work is
+ * enqueued on it; the calls return after the work has completed and write
+ * their host-side outputs then.
+ *
+ * Threads: calls are thread-safe; calls on different streams run
+ * independently.
+ */
+#ifndef RPCA_MI355X_H
+#define RPCA_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define RPCA_OK                 0  /* converged: ||M-L-S||_F < tol ||M||_F   */
+#define RPCA_NOT_CONVERGED      1  /* ran maxit iterations; L, S valid       */
+#define RPCA_ERR_ARG           -1  /* invalid argument; nothing was run      */
+#define RPCA_ERR_NOMEM         -2  /* device allocation failed               */
+#define RPCA_ERR_DEVICE        -3  /* HIP runtime error                      */
+#define RPCA_ERR_NONFINITE     -4  /* NaN or Inf in M (or in the iteration)  */
+#define RPCA_ERR_UNSUPPORTED   -5  /* shape not supported by this build      */
+/* Negative codes leave L and S unspecified. */
+
+/* ---- element types and contraction modes -------------------------------- */
+#define RPCA_F64 0   /* double storage, FP64 arithmetic throughout             */
+#define RPCA_F32 1   /* float storage and elementwise arithmetic; the Gram is
+                        accumulated in FP64 and the eigensolve is FP64        */
+
+#define RPCA_GRAM_DEFAULT 0  /* Gram and rebuild in the storage precision,
+                                Gram accumulated in FP64                      */
+#define RPCA_GRAM_BF16X3  1  /* F32 only: Gram and rebuild as split-BF16
+                                products (hi*hi + hi*lo + lo*hi) on MFMA with
+                                FP32 accumulation; eigensolve stays FP64      */
+
+#define RPCA_N_MAX 128   /* largest frame count n accepted                    */
+
+/*
+ * rpca_solve_f64 / rpca_solve_f32 - one RPCA solve.
+ *
+ *   M        device, m x n (layout above), not modified
+ *   m, n     rows (pixels) and columns (frames); m >= 1, 1 <= n <= RPCA_N_MAX
+ *   lambda   sparsity weight of Eq. 2; <= 0 selects 1/sqrt(max(m, n))
+ *   mu       fixed ALM penalty; <= 0 selects m*n / (4 sum|M_ij|) (Sec. II-A)
+ *   tol      stopping threshold delta; <= 0 runs exactly maxit iterations
+ *   maxit    iteration cap, >= 1
+ *   L, S     device, m x n outputs, written in full
+ *   iterations  host pointer (may be NULL): iterations performed
+ *
+ * Returns RPCA_OK, RPCA_NOT_CONVERGED or a negative code.  sum|M| == 0
+ * returns RPCA_OK with L = S = 0 after 0 iterations.  Any NaN/Inf in M
+ * returns RPCA_ERR_NONFINITE.  A NULL pointer, m < 1, n < 1, n > RPCA_N_MAX,
+ * maxit < 1 or overlapping M/L/S returns RPCA_ERR_ARG.
+ */
+int rpca_solve_f64(const double* M, int64_t m, int64_t n, double lambda, double mu,
+                   double tol, int32_t maxit, double* L, double* S,
+                   int32_t* iterations, void* stream);
+int rpca_solve_f32(const float* M, int64_t m, int64_t n, double lambda, double mu,
+                   double tol, int32_t maxit, float* L, float* S,
+                   int32_t* iterations, void* stream);
+
+/*
+ * One problem of a batch.  M, L, S are device pointers as above (float for
+ * RPCA_F32, double for RPCA_F64).  iterations, status and residual are
+ * written back by the library (host memory).  residual is the final
+ * ||M - L - S||_F / ||M||_F.
+ */
+typedef struct rpca_problem {
+    const void* M;
+    int64_t m, n;
+    double lambda, mu, tol;
+    int32_t maxit;
+    void* L;
+    void* S;
+    int32_t iterations;   /* out */
+    int32_t status;       /* out */
+    double residual;      /* out */
+} rpca_problem;
+
+/*
+ * rpca_solve_many - solve `count` independent problems of possibly different
+ * shapes together: every iteration of every active problem runs in the same
+ * launches, so the FP64 eigensolves of different problems overlap each other
+ * and the streaming passes fill the whole GPU.  Each problem's result is
+ * bitwise identical to the same problem solved alone with rpca_solve_*.
+ * dtype: RPCA_F64 or RPCA_F32.  gram_mode: RPCA_GRAM_DEFAULT or
+ * RPCA_GRAM_BF16X3 (RPCA_F32 only).  Returns the worst status over the
+ * problems (negative codes first) and records each problem's own status.
+ */
+int rpca_solve_many(rpca_problem* probs, int32_t count, int32_t dtype,
+                    int32_t gram_mode, void* stream);
+
+/*
+ * rpca_solve_ex - one problem with an explicit contraction mode (the
+ * precision variant).  Same contract as rpca_solve_many with count = 1.
+ */
+int rpca_solve_ex(rpca_problem* prob, int32_t dtype, int32_t gram_mode, void* stream);
+
+/* Device workspace in bytes that one solve of this shape holds while it runs
+ * (iterate buffers, reduction partials, Gram, projector, eigenvectors,
+ * state).  0 for an unsupported shape. */
+size_t rpca_footprint_bytes(int64_t m, int64_t n, int32_t dtype);
+
+/*
+ * Kernel timing (for measurement).  While enabled, every launch is bracketed
+ * by HIP events on the call's stream and the durations are accumulated:
+ * init pass, eigensolve launches and update-pass launches that did work, and
+ * the finalize pass.  update_bytes is the algorithmic traffic of the timed
+ * update passes: 5 words per matrix entry (read X, S, Y; write S, Y), 3 on
+ * the first iteration (S and Y start at zero and are not read).
+ */
+typedef struct rpca_profile {
+    double init_ms, eig_ms, update_ms, finalize_ms;
+    int64_t eig_launches, update_launches;
+    double update_bytes;
+    int64_t solves, iterations;
+} rpca_profile;
+
+void rpca_profile_enable(int on);
+/* Copy the accumulated figures to *out; reset them when reset != 0. */
+int rpca_profile_read(rpca_profile* out, int reset);
+
+/* Static description of a status code. */
+const char* rpca_strerror(int code);
+
+/* Detail of the last failure on the calling thread (the HIP call and its
+ * error string), or "" when the last call succeeded. */
+const char* rpca_last_error(void);
+
+/* Library version string. */
+const char* rpca_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPCA_MI355X_H */

@@ -1,0 +1,193 @@
+"""MI355X RPCA: Python binding of librpca_mi355x.so.
+
+The functions named like the C ABI (``rpca_solve_f32``, ``rpca_solve_f64``,
+``rpca_solve_many``, ...) marshal torch tensors to device pointers and call
+the library; ``solve`` / ``solve_many`` are the same calls with outputs
+allocated for the caller.  torch supplies device memory and the current HIP
+stream only.
+
+Matrix arguments are the Casorati matrix (pixels x frames) of paper Sec. II-A,
+column-major with leading dimension m: either a 2-D (m, n) tensor with
+strides (1, m) (the transpose of a contiguous (n, m) tensor), or a
+C-contiguous (n, H, W) image stack (m = H*W).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import (RPCA_OK, RPCA_NOT_CONVERGED, RPCA_ERR_ARG, RPCA_ERR_NOMEM,
+                   RPCA_ERR_DEVICE, RPCA_ERR_NONFINITE, RPCA_ERR_UNSUPPORTED,
+                   RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_GRAM_BF16X3, RPCA_N_MAX,
+                   RpcaProblem, RpcaProfile)
+
+__all__ = ["solve", "solve_many", "SolveResult", "casorati_shape", "rpca_solve_f32",
+           "rpca_solve_f64", "rpca_solve_many", "rpca_solve_ex", "rpca_footprint_bytes",
+           "rpca_strerror", "rpca_version", "rpca_last_error", "rpca_profile_enable", "rpca_profile_read",
+           "RPCA_OK", "RPCA_NOT_CONVERGED", "RPCA_ERR_ARG", "RPCA_ERR_NOMEM",
+           "RPCA_ERR_DEVICE", "RPCA_ERR_NONFINITE", "RPCA_ERR_UNSUPPORTED", "RPCA_F32",
+           "RPCA_F64", "RPCA_GRAM_DEFAULT", "RPCA_GRAM_BF16X3", "RPCA_N_MAX"]
+
+
+def _stream_ptr(t) -> int:
+    import torch
+    return int(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def casorati_shape(t) -> tuple[int, int]:
+    """(m, n) of a Casorati tensor in either accepted layout; raises otherwise."""
+    if t.dim() == 2:
+        m, n = int(t.shape[0]), int(t.shape[1])
+        if n == 1 or m == 1:
+            if t.is_contiguous() or t.t().is_contiguous():
+                return m, n
+        if t.stride(0) == 1 and t.stride(1) == m:
+            return m, n
+        raise ValueError("2-D input must be column-major (strides (1, m))")
+    if t.dim() == 3:
+        if not t.is_contiguous():
+            raise ValueError("3-D input must be a C-contiguous (n, H, W) stack")
+        return int(t.shape[1] * t.shape[2]), int(t.shape[0])
+    raise ValueError("input must be (m, n) column-major or (n, H, W)")
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return RPCA_F32
+    if t.dtype == torch.float64:
+        return RPCA_F64
+    raise TypeError("input must be float32 or float64")
+
+
+def _check_device(*ts):
+    dev = ts[0].device
+    if dev.type != "cuda":
+        raise ValueError("tensors must be on a HIP device (torch 'cuda')")
+    for t in ts:
+        if t.device != dev or t.dtype != ts[0].dtype:
+            raise ValueError("all tensors must share device and dtype")
+
+
+def rpca_solve_f32(M, m: int, n: int, lam: float, mu: float, tol: float, maxit: int, L, S,
+                   stream: Optional[int] = None) -> tuple[int, int]:
+    """C ``rpca_solve_f32`` on torch tensors (or raw device addresses as int)."""
+    return _solve_raw(_lib.load().rpca_solve_f32, M, m, n, lam, mu, tol, maxit, L, S, stream)
+
+
+def rpca_solve_f64(M, m: int, n: int, lam: float, mu: float, tol: float, maxit: int, L, S,
+                   stream: Optional[int] = None) -> tuple[int, int]:
+    """C ``rpca_solve_f64`` on torch tensors (or raw device addresses as int)."""
+    return _solve_raw(_lib.load().rpca_solve_f64, M, m, n, lam, mu, tol, maxit, L, S, stream)
+
+
+def _ptr(x) -> Optional[int]:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _solve_raw(fn, M, m, n, lam, mu, tol, maxit, L, S, stream):
+    if stream is None:
+        stream = _stream_ptr(M) if hasattr(M, "device") else 0
+    it = ctypes.c_int32(0)
+    rc = fn(_ptr(M), int(m), int(n), float(lam), float(mu), float(tol), int(maxit),
+            _ptr(L), _ptr(S), ctypes.byref(it), stream)
+    return int(rc), int(it.value)
+
+
+def rpca_solve_many(problems: Sequence[RpcaProblem], dtype: int, gram_mode: int = RPCA_GRAM_DEFAULT,
+                    stream: int = 0) -> int:
+    arr = (RpcaProblem * len(problems))(*problems)
+    rc = _lib.load().rpca_solve_many(arr, len(problems), int(dtype), int(gram_mode), stream)
+    for i, p in enumerate(problems):
+        p.iterations, p.status, p.residual = arr[i].iterations, arr[i].status, arr[i].residual
+    return int(rc)
+
+
+def rpca_solve_ex(problem: RpcaProblem, dtype: int, gram_mode: int, stream: int = 0) -> int:
+    return int(_lib.load().rpca_solve_ex(ctypes.byref(problem), int(dtype), int(gram_mode), stream))
+
+
+def rpca_footprint_bytes(m: int, n: int, dtype: int) -> int:
+    return int(_lib.load().rpca_footprint_bytes(int(m), int(n), int(dtype)))
+
+
+def rpca_strerror(code: int) -> str:
+    return _lib.load().rpca_strerror(int(code)).decode()
+
+
+def rpca_last_error() -> str:
+    return _lib.load().rpca_last_error().decode()
+
+
+def rpca_version() -> str:
+    return _lib.load().rpca_version().decode()
+
+
+def rpca_profile_enable(on: bool) -> None:
+    _lib.load().rpca_profile_enable(1 if on else 0)
+
+
+def rpca_profile_read(reset: bool = True) -> dict:
+    p = RpcaProfile()
+    _lib.load().rpca_profile_read(ctypes.byref(p), 1 if reset else 0)
+    return {name: getattr(p, name) for name, _ in RpcaProfile._fields_}
+
+
+@dataclass
+class SolveResult:
+    L: object
+    S: object
+    iterations: int
+    status: int
+    residual: float
+
+
+def _problem(M, L, S, lam, mu, tol, maxit) -> RpcaProblem:
+    m, n = casorati_shape(M)
+    p = RpcaProblem()
+    p.M, p.m, p.n = M.data_ptr(), m, n
+    p.lam = -1.0 if lam is None else float(lam)
+    p.mu = -1.0 if mu is None else float(mu)
+    p.tol, p.maxit = float(tol), int(maxit)
+    p.L, p.S = L.data_ptr(), S.data_ptr()
+    return p
+
+
+def solve(M, lam: Optional[float] = None, mu: Optional[float] = None, tol: float = 1e-7,
+          maxit: int = 500, gram_mode: int = RPCA_GRAM_DEFAULT) -> SolveResult:
+    """One RPCA solve of M; L and S are returned in M's layout.  A negative
+    status raises RuntimeError."""
+    import torch
+    _check_device(M)
+    dt = _dtype_code(M)
+    L = torch.empty_like(M)
+    S = torch.empty_like(M)
+    p = _problem(M, L, S, lam, mu, tol, maxit)
+    rc = rpca_solve_ex(p, dt, gram_mode, _stream_ptr(M))
+    if rc < 0:
+        raise RuntimeError(f"rpca solve failed: {rpca_strerror(rc)} ({rc}) {rpca_last_error()}")
+    return SolveResult(L, S, int(p.iterations), int(p.status), float(p.residual))
+
+
+def solve_many(Ms: Sequence, lam: Optional[float] = None, mu: Optional[float] = None,
+               tol: float = 1e-7, maxit: int = 500,
+               gram_mode: int = RPCA_GRAM_DEFAULT) -> list[SolveResult]:
+    """Batched solve (one set of launches per iteration for all problems)."""
+    import torch
+    if len(Ms) == 0:
+        return []
+    _check_device(*Ms)
+    dt = _dtype_code(Ms[0])
+    outs = [(torch.empty_like(M), torch.empty_like(M)) for M in Ms]
+    probs = [_problem(M, L, S, lam, mu, tol, maxit) for M, (L, S) in zip(Ms, outs)]
+    rc = rpca_solve_many(probs, dt, gram_mode, _stream_ptr(Ms[0]))
+    if rc < 0:
+        raise RuntimeError(f"rpca batch failed: {rpca_strerror(rc)} ({rc}) {rpca_last_error()}")
+    return [SolveResult(L, S, int(p.iterations), int(p.status), float(p.residual))
+            for (L, S), p in zip(outs, probs)]

@@ -1,0 +1,107 @@
+"""ctypes declarations of librpca_mi355x.so (the C ABI in include/rpca.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpca_mi355x.so")
+
+RPCA_OK = 0
+RPCA_NOT_CONVERGED = 1
+RPCA_ERR_ARG = -1
+RPCA_ERR_NOMEM = -2
+RPCA_ERR_DEVICE = -3
+RPCA_ERR_NONFINITE = -4
+RPCA_ERR_UNSUPPORTED = -5
+RPCA_F64 = 0
+RPCA_F32 = 1
+RPCA_GRAM_DEFAULT = 0
+RPCA_GRAM_BF16X3 = 1
+RPCA_N_MAX = 128
+
+EXPORTS = (
+    "rpca_solve_f64", "rpca_solve_f32", "rpca_solve_many", "rpca_solve_ex",
+    "rpca_footprint_bytes", "rpca_strerror", "rpca_version",
+    "rpca_profile_enable", "rpca_profile_read", "rpca_last_error",
+)
+
+
+class RpcaProblem(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_void_p),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("lam", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("maxit", ctypes.c_int32),
+        ("L", ctypes.c_void_p),
+        ("S", ctypes.c_void_p),
+        ("iterations", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("residual", ctypes.c_double),
+    ]
+
+
+class RpcaProfile(ctypes.Structure):
+    _fields_ = [
+        ("init_ms", ctypes.c_double),
+        ("eig_ms", ctypes.c_double),
+        ("update_ms", ctypes.c_double),
+        ("finalize_ms", ctypes.c_double),
+        ("eig_launches", ctypes.c_int64),
+        ("update_launches", ctypes.c_int64),
+        ("update_bytes", ctypes.c_double),
+        ("solves", ctypes.c_int64),
+        ("iterations", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library once; raise if it is missing (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch ships its own copy of the HIP runtime under the same soname.  Load
+    # torch first so the library binds to that one runtime instead of bringing
+    # a second copy into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"librpca_mi355x.so not found at {path}; build it with "
+            "`python -m paper_2506_10257_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    for name in ("rpca_solve_f64", "rpca_solve_f32"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, i64, i64, dbl, dbl, dbl, i32, vp, vp, ctypes.POINTER(i32), vp]
+        f.restype = ctypes.c_int
+    lib.rpca_solve_many.argtypes = [ctypes.POINTER(RpcaProblem), i32, i32, i32, vp]
+    lib.rpca_solve_many.restype = ctypes.c_int
+    lib.rpca_solve_ex.argtypes = [ctypes.POINTER(RpcaProblem), i32, i32, vp]
+    lib.rpca_solve_ex.restype = ctypes.c_int
+    lib.rpca_footprint_bytes.argtypes = [i64, i64, i32]
+    lib.rpca_footprint_bytes.restype = ctypes.c_size_t
+    lib.rpca_strerror.argtypes = [ctypes.c_int]
+    lib.rpca_strerror.restype = ctypes.c_char_p
+    lib.rpca_last_error.argtypes = []
+    lib.rpca_last_error.restype = ctypes.c_char_p
+    lib.rpca_version.argtypes = []
+    lib.rpca_version.restype = ctypes.c_char_p
+    lib.rpca_profile_enable.argtypes = [ctypes.c_int]
+    lib.rpca_profile_enable.restype = None
+    lib.rpca_profile_read.argtypes = [ctypes.POINTER(RpcaProfile), ctypes.c_int]
+    lib.rpca_profile_read.restype = ctypes.c_int
+    _lib = lib
+    return lib

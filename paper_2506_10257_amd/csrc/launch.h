@@ -1,0 +1,22 @@
+// Host-side launchers of the device kernels (internal to the library).
+#pragma once
+
+#include "common.h"
+
+namespace rpca {
+
+// Frame classes compiled for the register-resident streaming kernels.  A solve
+// with n frames runs on the smallest class >= n.
+constexpr int kClassesF32[] = {4, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 56, 60, 64};
+constexpr int kClassesF64[] = {4, 8, 10, 12, 16, 20, 24, 28, 32};
+
+enum StreamMode { kModeInit = 0, kModeUpdate = 1, kModeFinalize = 2 };
+
+// dtype 0 = FP64, 1 = FP32 (as RPCA_F64 / RPCA_F32).
+hipError_t launch_stream_f32(int nb, int mode, int grid, hipStream_t stream,
+                             const SolveDesc* descs, const WorkItem* items);
+hipError_t launch_stream_f64(int nb, int mode, int grid, hipStream_t stream,
+                             const SolveDesc* descs, const WorkItem* items);
+hipError_t launch_eig(int dtype, int grid, hipStream_t stream, const SolveDesc* descs);
+
+}  // namespace rpca

@@ -1,0 +1,331 @@
+// Streaming kernels of the RPCA iteration (paper Sec. II-A, Eqs. 4-6).
+//
+// One thread owns one pixel row p of the Casorati matrix and holds its n
+// frame values in registers (n <= NB, NB a compile-time frame class).  Frame
+// j of row p sits at p + j*m, so for every j a wavefront reads 64 consecutive
+// pixels: each load instruction is one coalesced 256 B (FP32) / 512 B (FP64)
+// segment.  A workgroup walks tiles of kTile rows.
+//
+// k_stream<INIT=true>   : one pass over X.  sum|X|, sum X^2, non-finite count
+//                         (for mu and the stopping test) and the Gram X^T X,
+//                         which is the Gram of the first iterate because S and
+//                         Y start at zero.
+// k_stream<INIT=false>  : one ALM iteration k for every row, fused:
+//                           a  = x - s + y/mu                  (argument of Eq. 4)
+//                           l  = a P      P = V diag(w) V^T  (Eq. 4 rebuild)
+//                           t  = x - l + y/mu
+//                           s' = shrink_{lam/mu}(t)           (Eq. 5)
+//                           z  = x - l - s'
+//                           y' = y + mu z                      (Eq. 6)
+//                           r2 += z^2                          (stopping test)
+//                           a' = x - s' + y'/mu  -> Gram of the next iterate
+//                         reading X, S_{k-1}, Y_{k-1} and writing S_k, Y_k:
+//                         five words per matrix entry and iteration.
+// k_finalize            : L = A_k P_k for the last iterate (same arithmetic as
+//                         the rebuild above) and S_k, into the caller's buffers.
+//
+// Reductions never use floating-point atomics.  Each workgroup writes its
+// partial sums to a fixed slot; the last workgroup to arrive in a group of
+// kGroup slots adds them in slot order, and the eigensolve kernel adds the
+// group sums in group order.  The result depends only on the solve's own
+// shape, so it is bitwise the same whether the solve runs alone or in a batch.
+#pragma once
+
+#include "common.h"
+
+namespace rpca {
+
+__device__ inline void blk_coords(int blk, int& bi, int& bj) {
+  int j = 0;
+  while ((j + 1) * (j + 2) / 2 <= blk) ++j;
+  bj = j;
+  bi = blk - j * (j + 1) / 2;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline float clamp_sym(float v, float g) { return fminf(fmaxf(v, -g), g); }
+__device__ inline double clamp_sym(double v, double g) { return fmin(fmax(v, -g), g); }
+__device__ inline bool finite_val(float v) { return __builtin_isfinite(v); }
+__device__ inline bool finite_val(double v) { return __builtin_isfinite(v); }
+
+// First level of the fixed-order reduction.  Every workgroup writes its own
+// partial slot; the last workgroup to arrive in a group of kGroup consecutive
+// slots adds the group's slots in slot order into the group partial.  The
+// eigensolve kernel of the next step adds the group partials in group order.
+__device__ inline void reduce_group(const SolveDesc& d, int slot, int nent, int* s_flag) {
+  const int tid = threadIdx.x;
+  __threadfence();
+  __syncthreads();
+  const int g = slot / kGroup;
+  const int lo = g * kGroup;
+  const int cnt = min(lo + kGroup, d.slots) - lo;
+  if (tid == 0) {
+    const uint32_t prev = __hip_atomic_fetch_add(&d.counters[g], 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    *s_flag = (prev == static_cast<uint32_t>(cnt - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!*s_flag) return;
+  __threadfence();
+  const double* src = d.partials + static_cast<size_t>(lo) * d.pstride;
+  for (int idx = tid; idx < nent; idx += blockDim.x) {
+    // all loads of the group in flight at once, then the sum in slot order
+    double v[kGroup];
+#pragma unroll
+    for (int q = 0; q < kGroup; ++q) v[q] = q < cnt ? src[static_cast<size_t>(q) * d.pstride + idx] : 0.0;
+    double s = v[0];
+#pragma unroll
+    for (int q = 1; q < kGroup; ++q)
+      if (q < cnt) s += v[q];
+    d.gpartials[static_cast<size_t>(g) * d.pstride + idx] = s;
+  }
+  if (tid == 0) d.counters[g] = 0u;
+}
+
+template <typename T, int NB, bool INIT>
+__global__ void __launch_bounds__(kThreads)
+k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+  constexpr int NB4 = (NB + 3) / 4 * 4;
+  constexpr int LDT = kTile + 1;  // odd row stride: frames of one row fall in different banks
+  constexpr size_t kTileBytes = sizeof(T) * NB4 * LDT;
+  constexpr size_t kRedBytes = sizeof(double) * kThreads * 16;
+  constexpr size_t kSmem = kTileBytes > kRedBytes ? kTileBytes : kRedBytes;
+  __shared__ __align__(16) unsigned char smem[kSmem];
+  __shared__ double wred[kThreads / 64][kScalars];
+  __shared__ int s_flag;
+  T* tileA = reinterpret_cast<T*>(smem);
+  double* red = reinterpret_cast<double*>(smem);
+
+  const int tid = threadIdx.x;
+  const int64_t t_begin = RPCA_NOW();
+  const WorkItem wi = items[blockIdx.x];
+  const SolveDesc& d = descs[wi.solve];
+  SolveState* st = d.st;
+  int k = 0;
+  if constexpr (!INIT) {
+    if (st->done) return;
+    k = st->iter;
+  }
+  const int n = d.n;
+  const int64_t m = d.m;
+  const gptr<const T> X = as_global<T>(d.X);
+  const gptr<const T> Sin = as_global<T>(static_cast<const void*>(d.S[(k + 1) & 1]));
+  const gptr<const T> Yin = as_global<T>(static_cast<const void*>(d.Y[(k + 1) & 1]));
+  const gptr<T> Sout = as_global<T>(d.S[k & 1]);
+  const gptr<T> Yout = as_global<T>(d.Y[k & 1]);
+  const cptr<T> P = as_const<T>(d.P);
+  const bool first = (k == 1);
+  T mu = 0, imu = 0, gam = 0;
+  if constexpr (!INIT) {
+    mu = static_cast<T>(st->mu);
+    imu = static_cast<T>(st->imu);
+    gam = static_cast<T>(st->gamma);
+  }
+
+  // Gram work split: 4x4 blocks of frames x row chunks.
+  const int nblk = gram_blocks((n + 3) >> 2);
+  const int C = kThreads / nblk;
+  const int gblk = tid / C;
+  const int gc = tid - gblk * C;
+  const bool gact = gblk < nblk;
+  int bi = 0, bj = 0;
+  if (gact) blk_coords(gblk, bi, bj);
+  double gacc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) gacc[e] = 0.0;
+  double r2 = 0.0, s1 = 0.0, s2 = 0.0, nf = 0.0;
+
+  const int t0 = wi.slot * d.tps;
+  const int t1 = min(t0 + d.tps, d.tiles);
+  for (int t = t0; t < t1; ++t) {
+    // row index within the solve; m < 2^30 so byte offsets fit 32 bits
+    const uint32_t p = static_cast<uint32_t>(t) * kTile + tid;
+    const bool valid = p < m;
+    if constexpr (INIT) {
+#pragma unroll
+      for (int j = 0; j < NB4; ++j) {
+        T x = 0;
+        if (j < n && valid) x = (X + static_cast<size_t>(j) * m)[p];
+        const double xd = static_cast<double>(x);
+        s1 += fabs(xd);
+        s2 = fma(xd, xd, s2);
+        nf += finite_val(x) ? 0.0 : 1.0;
+        tileA[j * LDT + tid] = x;
+      }
+    } else {
+      T x[NB], y[NB], a[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        x[j] = 0; y[j] = 0; a[j] = 0;
+        if (j < n) {
+          if (valid) {
+            const size_t col = static_cast<size_t>(j) * m;
+            T s = 0;
+            x[j] = (X + col)[p];
+            if (!first) {
+              s = (Sin + col)[p];
+              y[j] = (Yin + col)[p];
+            }
+            a[j] = fma(y[j], imu, x[j] - s);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NB4; ++j) {
+        T apj = 0;
+        if (j < NB && j < n) {
+          // Eq. 4 rebuild: l = sum_i a_i P_ij (P is zero outside n x n).
+          T l = 0;
+#pragma unroll
+          for (int i = 0; i < NB; ++i) l = fma(a[i], P[i * NB + j], l);
+          const T tt = fma(y[j], imu, x[j]) - l;          // X - L + Y/mu
+          const T sn = tt - clamp_sym(tt, gam);            // Eq. 5 shrink
+          const T z = (x[j] - l) - sn;                     // X - L - S
+          const T yn = fma(mu, z, y[j]);                   // Eq. 6
+          const double zd = static_cast<double>(z);
+          r2 = fma(zd, zd, r2);
+          apj = fma(yn, imu, x[j] - sn);                   // next X - S + Y/mu
+          if (valid) {
+            const size_t col = static_cast<size_t>(j) * m;
+            (Sout + col)[p] = sn;
+            (Yout + col)[p] = yn;
+          } else {
+            apj = 0;
+          }
+        }
+        tileA[j * LDT + tid] = apj;
+      }
+    }
+    __syncthreads();
+    if (gact) {
+      const T* u = tileA + (4 * bi) * LDT;
+      const T* v = tileA + (4 * bj) * LDT;
+      for (int r = gc; r < kTile; r += C) {
+        double ue[4], vf[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          ue[e] = static_cast<double>(u[e * LDT + r]);
+          vf[e] = static_cast<double>(v[e * LDT + r]);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int f = 0; f < 4; ++f) gacc[e * 4 + f] = fma(ue[e], vf[f], gacc[e * 4 + f]);
+      }
+    }
+    __syncthreads();
+  }
+
+#ifdef RPCA_TRACE
+  const int64_t t_tiles = RPCA_NOW();
+#endif
+  // Workgroup partial: scalars by wave shuffles then waves in order; Gram
+  // blocks by chunk in order.
+  double sc[kScalars] = {r2, s1, s2, nf};
+#pragma unroll
+  for (int s = 0; s < kScalars; ++s) sc[s] = wave_sum(sc[s]);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int s = 0; s < kScalars; ++s) wred[tid >> 6][s] = sc[s];
+  }
+  if (gact) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) red[(gblk * C + gc) * 16 + e] = gacc[e];
+  }
+  __syncthreads();
+  double* part = d.partials + static_cast<size_t>(wi.slot) * d.pstride;
+  for (int idx = tid; idx < nblk * 16; idx += kThreads) {
+    const int blk = idx >> 4, e = idx & 15;
+    double s = 0.0;
+    for (int c = 0; c < C; ++c) s += red[(blk * C + c) * 16 + e];
+    part[kScalars + idx] = s;
+  }
+  if (tid < kScalars) {
+    double s = wred[0][tid];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; ++w) s += wred[w][tid];
+    part[tid] = s;
+  }
+#ifdef RPCA_TRACE
+  if (tid == 0 && d.wgtrace) {
+    d.wgtrace[wi.slot * 4 + 0] = t_begin;
+    d.wgtrace[wi.slot * 4 + 1] = t_tiles;
+    d.wgtrace[wi.slot * 4 + 2] = RPCA_NOW();
+  }
+#else
+  (void)t_begin;
+#endif
+  reduce_group(d, wi.slot, kScalars + nblk * 16, &s_flag);
+#ifdef RPCA_TRACE
+  if (tid == 0 && d.wgtrace) d.wgtrace[wi.slot * 4 + 3] = RPCA_NOW();
+#endif
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(kThreads)
+k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+  const int tid = threadIdx.x;
+  const WorkItem wi = items[blockIdx.x];
+  const SolveDesc& d = descs[wi.solve];
+  const SolveState* st = d.st;
+  if (st->status < 0) return;
+  const int k = st->iter;
+  const int n = d.n;
+  const int64_t m = d.m;
+  const gptr<const T> X = as_global<T>(d.X);
+  const gptr<const T> Sprev = as_global<T>(static_cast<const void*>(d.S[(k + 1) & 1]));
+  const gptr<const T> Yprev = as_global<T>(static_cast<const void*>(d.Y[(k + 1) & 1]));
+  const gptr<const T> Sk = as_global<T>(static_cast<const void*>(d.S[k & 1]));
+  const cptr<T> P = as_const<T>(d.P);
+  const gptr<T> L = as_global<T>(d.Lout);
+  const gptr<T> So = as_global<T>(d.Sout);
+  const bool first = (k == 1);
+  const T imu = static_cast<T>(st->imu);
+  const int t0 = wi.slot * d.tps;
+  const int t1 = min(t0 + d.tps, d.tiles);
+  for (int t = t0; t < t1; ++t) {
+    const uint32_t p = static_cast<uint32_t>(t) * kTile + tid;
+    if (p >= m) break;
+    if (k == 0) {  // sum|X| == 0: L = S = 0
+      for (int j = 0; j < n; ++j) {
+        const size_t col = static_cast<size_t>(j) * m;
+        (L + col)[p] = T(0);
+        (So + col)[p] = T(0);
+      }
+      continue;
+    }
+    T a[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      a[j] = 0;
+      if (j < n) {
+        const size_t col = static_cast<size_t>(j) * m;
+        const T x = (X + col)[p];
+        T s = 0, y = 0;
+        if (!first) {
+          s = (Sprev + col)[p];
+          y = (Yprev + col)[p];
+        }
+        a[j] = fma(y, imu, x - s);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < n) {
+        T l = 0;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) l = fma(a[i], P[i * NB + j], l);
+        const size_t col = static_cast<size_t>(j) * m;
+        (L + col)[p] = l;
+        (So + col)[p] = (Sk + col)[p];
+      }
+    }
+  }
+}
+
+}  // namespace rpca

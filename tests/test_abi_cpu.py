@@ -1,0 +1,90 @@
+"""The C-ABI library loads, exports every symbol include/rpca.h declares, and
+rejects invalid arguments on the host before touching a device.  No compute
+call runs here (no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2506_10257_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rpca.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpca_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("rpca_solve_f64", "rpca_solve_f32", "rpca_solve_many",
+                 "rpca_footprint_bytes", "rpca_strerror"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_lib.EXPORTS) <= set(_declared())
+
+
+def test_strerror_and_version(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert lib.rpca_strerror(code)
+    assert lib.rpca_strerror(99) == b"unknown status"
+    assert lib.rpca_version().startswith(b"rpca_mi355x")
+
+
+def test_footprint(lib):
+    f32 = lib.rpca_footprint_bytes(262144, 20, _lib.RPCA_F32)
+    f64 = lib.rpca_footprint_bytes(262144, 20, _lib.RPCA_F64)
+    mat32 = 262144 * 20 * 4
+    assert 4 * mat32 <= f32 < 4 * mat32 + (4 << 20)
+    assert 8 * mat32 <= f64 < 8 * mat32 + (8 << 20)
+    assert lib.rpca_footprint_bytes(0, 20, _lib.RPCA_F32) == 0
+    assert lib.rpca_footprint_bytes(100, 0, _lib.RPCA_F32) == 0
+    assert lib.rpca_footprint_bytes(100, 129, _lib.RPCA_F32) == 0
+    assert lib.rpca_footprint_bytes(100, 20, 7) == 0
+
+
+def _call(lib, M, m, n, L, S, maxit=10, fn="rpca_solve_f32"):
+    it = ctypes.c_int32(-7)
+    rc = getattr(lib, fn)(M, m, n, -1.0, -1.0, 1e-6, maxit, L, S, ctypes.byref(it), None)
+    return rc, it.value
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    A, B, C = 1 << 40, 2 << 40, 3 << 40       # disjoint fake device ranges
+    assert _call(lib, None, 100, 4, B, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 4, None, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 4, B, None)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 0, 4, B, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 0, B, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 129, B, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 4, B, C, maxit=0)[0] == _lib.RPCA_ERR_ARG
+    # overlapping M / L / S
+    assert _call(lib, A, 100, 4, A + 16, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 4, B, B + 1596)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 4, B, B, fn="rpca_solve_f64")[0] == _lib.RPCA_ERR_ARG
+    # iterations is written as 0 on failure
+    assert _call(lib, None, 100, 4, B, C)[1] == 0
+
+
+def test_batch_argument_checks(lib):
+    P = _lib.RpcaProblem
+    arr = (P * 1)()
+    assert lib.rpca_solve_many(arr, 0, _lib.RPCA_F32, 0, None) == _lib.RPCA_ERR_ARG
+    assert lib.rpca_solve_many(arr, 1, 5, 0, None) == _lib.RPCA_ERR_ARG
+    assert lib.rpca_solve_many(arr, 1, _lib.RPCA_F32, 9, None) == _lib.RPCA_ERR_ARG
+    assert lib.rpca_solve_many(arr, 1, _lib.RPCA_F32, 0, None) == _lib.RPCA_ERR_ARG  # NULL M

@@ -1,0 +1,46 @@
+"""Batched solves: each problem's result inside rpca_solve_many is bitwise
+the one it gets alone, and matches the oracle."""
+import numpy as np
+import pytest
+
+import paper_2506_10257_amd as rp
+from oracle import rpca, rel_fro
+from synth import batch_window
+from tests.gpu_helpers import to_dev, to_host, gpu_solve, report
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 64, 10), (96, 128, 20), (128, 128, 12), (80, 96, 20), (64, 48, 7)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batch_bitwise_equals_alone(dtype):
+    import torch
+    wins = [batch_window(H, W, n, 7000 + i) for i, (H, W, n) in enumerate(SHAPES)]
+    Xs = [w.X().astype(dtype) for w in wins]
+    Ms = [to_dev(X, dtype) for X in Xs]
+    res = rp.solve_many(Ms, tol=1e-6, maxit=400)
+    torch.cuda.synchronize()
+    for X, r in zip(Xs, res):
+        L, S, it, rc, _ = gpu_solve(X, dtype, tol=1e-6, maxit=400)
+        same = torch.equal(L, r.L) and torch.equal(S, r.S)
+        report("batch-vs-alone", m=X.shape[0], n=X.shape[1], it=r.iterations, it_alone=it,
+               bitwise=int(same))
+        assert r.iterations == it and r.status == rc
+        assert same
+
+
+def test_batch_matches_oracle_fp32():
+    import torch
+    wins = [batch_window(H, W, n, 7100 + i) for i, (H, W, n) in enumerate(SHAPES[:3])]
+    Xs = [w.X().astype(np.float32) for w in wins]
+    res = rp.solve_many([to_dev(X, np.float32) for X in Xs], tol=1e-6, maxit=400)
+    torch.cuda.synchronize()
+    for X, r in zip(Xs, res):
+        ref = rpca(X.astype(np.float64), tol=1e-6, maxit=400)
+        relL = rel_fro(to_host(r.L), ref.L)
+        relS = rel_fro(to_host(r.S), ref.S)
+        report("batch-vs-oracle", m=X.shape[0], n=X.shape[1], it=r.iterations,
+               it_ref=ref.iterations, relL=relL, relS=relS)
+        assert abs(r.iterations - ref.iterations) <= 1
+        assert relL <= 1e-4 and relS <= 1e-4

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: FP64 path within 1e-10 relative Frobenius error in L and S with the
+same iteration count; FP32 path within 1e-4 with the iteration count +-1;
+the thresholded bound-bubble mask of L agrees with Dice >= 0.999.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import rpca, rel_fro, dice, bound_threshold
+from synth import window_128x128x20, window_512x512x20, planted_low_rank_sparse
+from tests.gpu_helpers import gpu_solve, to_host, report
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_512x512x20.npz")
+
+
+def _compare(name, X, dtype, ref, theta=None, tol_rel=None, it_slack=None, **kw):
+    L, S, it, rc, M = gpu_solve(X, dtype, **kw)
+    Lh, Sh = to_host(L), to_host(S)
+    relL, relS = rel_fro(Lh, ref.L), rel_fro(Sh, ref.S)
+    d = dice(Lh >= theta, ref.L >= theta) if theta is not None else 1.0
+    report(name, dtype=np.dtype(dtype).name, it=it, it_ref=ref.iterations, rc=rc,
+           relL=relL, relS=relS, dice=d)
+    if tol_rel is None:
+        tol_rel = 1e-10 if dtype == np.float64 else 1e-4
+    if it_slack is None:
+        it_slack = 0 if dtype == np.float64 else 1
+    assert abs(it - ref.iterations) <= it_slack
+    if it_slack == 0:
+        assert rc == ref.status
+    assert relL <= tol_rel, relL
+    assert relS <= tol_rel, relS
+    assert d >= 0.999
+    return Lh, Sh, it, rc
+
+
+# ------------------------------------------------- 128x128 x 20 window (full)
+@pytest.fixture(scope="module")
+def win128():
+    w = window_128x128x20()
+    theta = bound_threshold(w.L_gt, w.bound_mask)
+    return w, theta
+
+
+@pytest.fixture(scope="module")
+def ref128(win128):
+    w, _ = win128
+    return rpca(w.X(), lam=1.0 / 128, tol=1e-7, maxit=500)
+
+
+def test_128x128x20_fp64_full_solve(win128, ref128):
+    w, theta = win128
+    _compare("128x128x20 maxit500", w.X(), np.float64, ref128, theta,
+             lam=1.0 / 128, tol=1e-7, maxit=500)
+
+
+def test_128x128x20_fp32_full_solve(win128):
+    w, theta = win128
+    X32 = w.X().astype(np.float32)
+    ref = rpca(X32.astype(np.float64), lam=1.0 / 128, tol=1e-7, maxit=500)
+    _compare("128x128x20 maxit500", X32, np.float32, ref, theta, lam=1.0 / 128, tol=1e-7, maxit=500)
+
+
+@pytest.mark.timeout(300)
+def test_128x128x20_fp64_to_convergence(win128):
+    """Run to the stopping test (the oracle converges after ~800 iterations)."""
+    w, theta = win128
+    ref = rpca(w.X(), lam=1.0 / 128, tol=1e-7, maxit=1500)
+    assert ref.status == 0
+    _compare("128x128x20 converge", w.X(), np.float64, ref, theta, lam=1.0 / 128, tol=1e-7, maxit=1500)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 25])
+def test_iterate_parity_fp64(win128, k):
+    """tol <= 0 runs exactly k iterations: compare the k-th iterate."""
+    w, _ = win128
+    X = np.asfortranarray(w.X()[:5000])          # 19 full tiles and a ragged one
+    ref = rpca(X, tol=0.0, maxit=k)
+    _compare(f"iterate k={k}", X, np.float64, ref, None, tol=0.0, maxit=k)
+
+
+@pytest.mark.parametrize("k", [1, 3, 25])
+def test_iterate_parity_fp32(win128, k):
+    w, _ = win128
+    X = np.asfortranarray(w.X()[:5000]).astype(np.float32)
+    ref = rpca(X.astype(np.float64), tol=0.0, maxit=k)
+    _compare(f"iterate k={k}", X, np.float32, ref, None, tol=0.0, maxit=k)
+
+
+# ---------------------------------------------------------- shapes and tails
+def _planted(m, n, seed):
+    r = max(1, min(m, n) // 5)
+    L0, S0 = planted_low_rank_sparse(m, n, r, 0.05, seed)
+    rng = np.random.default_rng(seed + 1)
+    return np.asfortranarray(L0 + S0 + 1e-3 * rng.standard_normal((m, n)))
+
+
+SHAPES64 = [(1, 3), (37, 1), (257, 5), (1000, 7), (3001, 10), (4099, 13), (2049, 20),
+            (3000, 24), (777, 32)]
+SHAPES32 = SHAPES64 + [(1500, 40), (1200, 60), (1100, 64)]
+
+
+@pytest.mark.parametrize("m,n", SHAPES64)
+def test_shapes_fp64(m, n):
+    X = _planted(m, n, 100 + m + n)
+    ref = rpca(X, tol=1e-6, maxit=300)
+    _compare(f"shape {m}x{n}", X, np.float64, ref, None, tol=1e-6, maxit=300)
+
+
+@pytest.mark.parametrize("m,n", SHAPES32)
+def test_shapes_fp32(m, n):
+    X = _planted(m, n, 200 + m + n).astype(np.float32)
+    ref = rpca(X.astype(np.float64), tol=1e-6, maxit=300)
+    _compare(f"shape {m}x{n}", X, np.float32, ref, None, tol=1e-6, maxit=300)
+
+
+# ------------------------------------------------------------ special cases
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_zero_input(dtype):
+    X = np.zeros((1000, 12))
+    L, S, it, rc, M = gpu_solve(X, dtype, tol=1e-7, maxit=50)
+    assert rc == 0 and it == 0
+    assert not to_host(L).any() and not to_host(S).any()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_nonfinite_input(dtype, bad):
+    X = np.ones((700, 6))
+    X[333, 4] = bad
+    _, _, it, rc, _ = gpu_solve(X, dtype, tol=1e-7, maxit=50)
+    assert rc == -4 and it == 0
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_input_untouched_and_maxit_one(dtype):
+    X = _planted(900, 8, 5).astype(dtype)
+    L, S, it, rc, M = gpu_solve(X, dtype, tol=1e-9, maxit=1)
+    assert rc == 1 and it == 1
+    assert np.array_equal(to_host(M), X.astype(np.float64))
+    ref = rpca(X.astype(np.float64), tol=1e-9, maxit=1)
+    tol_rel = 1e-12 if dtype == np.float64 else 1e-5
+    assert rel_fro(to_host(L), ref.L) <= tol_rel
+    assert rel_fro(to_host(S), ref.S) <= tol_rel
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_lambda_special_cases(dtype):
+    """lam > 1 gives (L, S) -> (X, 0); lam < 1/sqrt(mn) gives (0, X)."""
+    rng = np.random.default_rng(3)
+    X = np.asfortranarray(rng.standard_normal((64, 8)) + 1.0).astype(dtype)
+    # FP32 storage cannot reach a 1e-9 relative residual: use 1e-6 there.
+    tol = 1e-9 if dtype == np.float64 else 1e-6
+    for lam in (1.1, 0.9 / np.sqrt(X.size)):
+        ref = rpca(X.astype(np.float64), lam=lam, tol=tol, maxit=3000)
+        _compare(f"lambda={lam:.3g}", X, dtype, ref, None,
+                 tol_rel=1e-9 if dtype == np.float64 else 2e-4, lam=lam, tol=tol, maxit=3000)
+
+
+# ------------------------------------------------- 512x512 x 20 window (full)
+@pytest.fixture(scope="module")
+def win512():
+    return window_512x512x20()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_512x512x20_iterate_parity(win512, dtype):
+    """Full size, first iterates against the live oracle."""
+    X = win512.X().astype(dtype)
+    ref = rpca(X.astype(np.float64), lam=1.0 / 512, tol=0.0, maxit=3)
+    _compare("512x512x20 k=3", X, dtype, ref, None, lam=1.0 / 512, tol=0.0, maxit=3)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_512x512x20_full_solve_vs_stored_oracle(win512, dtype):
+    """Full solve against the stored summary of the oracle's full solve
+    (tests/golden/make_oracle_summaries.py)."""
+    if not os.path.exists(GOLDEN):
+        pytest.skip("oracle summary not generated")
+    g = np.load(GOLDEN)
+    X = win512.X()
+    L, S, it, rc, M = gpu_solve(X.astype(dtype), dtype, lam=1.0 / 512, tol=1e-6, maxit=1000)
+    Lh, Sh = to_host(L), to_host(S)
+    m, n = X.shape
+    idx = g["sample_idx"]
+    Lf, Sf = Lh.ravel(order="F"), Sh.ravel(order="F")
+    # entrywise sample errors relative to the RMS entry of the oracle's L and S
+    eL = np.abs(Lf[idx] - g["L_sample"]).max() / (float(g["L_fro"]) / np.sqrt(m * n))
+    eS = np.abs(Sf[idx] - g["S_sample"]).max() / (float(g["S_fro"]) / np.sqrt(m * n))
+    nL = abs(np.linalg.norm(Lh) - float(g["L_fro"])) / float(g["L_fro"])
+    nS = abs(np.linalg.norm(Sh) - float(g["S_fro"])) / float(g["S_fro"])
+    mask_ref = np.unpackbits(g["mask_bits"])[: m * n].astype(bool)
+    d = dice(Lf >= float(g["theta"]), mask_ref)
+    resid = np.linalg.norm(X - Lh - Sh) / np.linalg.norm(X)
+    report("512x512x20 full", dtype=np.dtype(dtype).name, it=it, it_ref=int(g["iterations"]),
+           rc=rc, sampleL=eL, sampleS=eS, normL=nL, normS=nS, dice=d, resid=resid)
+    slack = 0 if dtype == np.float64 else 1
+    assert abs(it - int(g["iterations"])) <= slack
+    bar = 1e-9 if dtype == np.float64 else 1e-3
+    assert eL <= bar and eS <= bar
+    assert nL <= bar and nS <= bar
+    assert d >= 0.999
+    if rc == 0:
+        assert resid < 1e-6 * (1 + (1e-3 if dtype == np.float32 else 0))
