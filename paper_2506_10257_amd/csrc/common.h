@@ -51,7 +51,6 @@ struct SolveDesc {
   void* P;                // nb x nb thresholding projector, storage precision
   double* V;              // nb x nb eigenvectors of the last eigensolve
   SolveState* st;
-  uint32_t* counters;     // groups + 1 arrival counters (zero between launches)
   int64_t* wgtrace;       // per-slot timestamps (trace builds only, else null)
   int64_t m;
   int32_t n, nb;          // frames and the compiled frame class (n <= nb)
@@ -96,6 +95,11 @@ __device__ inline cptr<T> as_const(const void* p) {
 struct WorkItem {
   int32_t solve;   // index into the SolveDesc array of the launch
   int32_t slot;    // which tiles: [slot * tps, min((slot + 1) * tps, tiles))
+};
+
+struct GroupItem {
+  int32_t solve;   // index into the SolveDesc array of the launch
+  int32_t group;   // slots [group * kGroup, min((group + 1) * kGroup, slots))
 };
 
 // Gram blocks: 4 x 4 blocks (bi <= bj) of the n x n Gram, packed by column

@@ -16,45 +16,177 @@
 //      iteration, V <- V (3I - V^T V) / 2: without it the rounding of the
 //      rotations accumulates over hundreds of iterations and the projector
 //      drifts away from an orthogonal one;
-//   3. cyclic two-sided Jacobi in LDS with the round-robin parallel ordering:
-//      each round rotates n/2 disjoint (p, q) pairs at once, so a round is
-//      one barrier-separated update of all of G and V;
+//   3. cyclic two-sided Jacobi in LDS with the round-robin parallel ordering
+//      (each index meets every other once per sweep, n/2 disjoint pairs per
+//      round).  G and V are double-buffered: a round reads one copy and
+//      writes J^T G J and V J into the other, and the threads that own the
+//      next round's pairs compute that round's rotations in the same phase,
+//      so a round costs one barrier;
 //   4. w from the eigenvalues, P = V diag(w) V^T in the storage precision.
 //
-// The rotation of a pair uses the symmetric 2x2 Schur decomposition
-// (tan t of the smaller angle; Golub & Van Loan, Matrix Computations,
-// Sec. 8.5).  A pair is rotated while |g_pq| > eps sqrt(g_pp g_qq), the
-// relative off-diagonal test that gives eigenvalues to high relative accuracy.
+// The rotation of a pair is the symmetric 2x2 Schur decomposition with the
+// smaller angle (Golub & Van Loan, Matrix Computations, Sec. 8.5), written
+// with one division: t = sgn(d) 2 g_pq / (|d| + sqrt(d^2 + 4 g_pq^2)),
+// d = g_qq - g_pp, c = 1/sqrt(1 + t^2), s = t c.  A pair is rotated while
+// g_pq^2 > eps^2 |g_pp g_qq| (relative off-diagonal test); eps is 1e-15 for
+// FP64 solves and 1e-11 for FP32 solves, whose data carry 6e-8 rounding.
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
 namespace rpca {
 namespace {
 
-constexpr int LD = kEigMaxN + 1;
-constexpr double kRotEps = 1.0e-15;
-constexpr double kTiny = 1.0e-300;
+constexpr double kTiny2 = 1.0e-300;
 constexpr int kMaxSweeps = 40;
-constexpr int kMaxUpper = (kEigMaxN * (kEigMaxN + 1) / 2 + kEigThreads - 1) / kEigThreads;
-constexpr int kMaxFull = (kEigMaxN * kEigMaxN + kEigThreads - 1) / kEigThreads;
-
-__device__ inline bool off_diag_large(double gij, double gii, double gjj) {
-  const double a = fabs(gij);
-  return a > kTiny && a > kRotEps * sqrt(fabs(gii * gjj));
-}
 
 template <typename T>
-__global__ void __launch_bounds__(kEigThreads) k_eig(const SolveDesc* __restrict__ descs) {
-  __shared__ double G[kEigMaxN * LD];
-  __shared__ double V[kEigMaxN * LD];
-  __shared__ double C[kEigMaxN * LD];
-  __shared__ double al[kEigMaxN], be[kEigMaxN], dg[kEigMaxN], w[kEigMaxN];
-  __shared__ int uu[kEigMaxN], vv[kEigMaxN], partner[kEigMaxN];
+struct RotEps;
+template <>
+struct RotEps<double> {
+  static constexpr double eps2 = 1.0e-30;
+};
+template <>
+struct RotEps<float> {
+  static constexpr double eps2 = 1.0e-22;
+};
+
+template <typename T>
+__device__ inline bool off_diag_large(double gij, double gii, double gjj) {
+  const double a2 = gij * gij;
+  return a2 > kTiny2 && a2 > RotEps<T>::eps2 * fabs(gii * gjj);
+}
+
+// Round-robin pairing of round r (0 <= r < N2-1) over N2 (even) indices:
+// pair 0 is (N2-1, r), pair k >= 1 is ((r+k) mod M, (r-k) mod M), M = N2-1.
+__device__ inline void pair_indices(int r, int k, int N2, int& p, int& q) {
+  const int M = N2 - 1;
+  int a, b;
+  if (k == 0) {
+    a = N2 - 1;
+    b = r;
+  } else {
+    a = r + k;
+    if (a >= M) a -= M;
+    b = r - k;
+    if (b < 0) b += M;
+  }
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// Pair number and partner of index i in round r (branch-free).
+__device__ inline void pair_of(int i, int r, int N2, int& k, int& partner) {
+  const int M = N2 - 1;
+  int d1 = i - r;
+  d1 += d1 < 0 ? M : 0;
+  const bool low = d1 < (N2 >> 1);
+  const int kk = low ? d1 : M - d1;
+  int pp = low ? r - d1 : r + kk;
+  pp += pp < 0 ? M : 0;
+  pp -= pp >= M ? M : 0;
+  const bool last = i == N2 - 1;
+  const bool isr = i == r;
+  k = (last || isr) ? 0 : kk;
+  partner = last ? r : (isr ? N2 - 1 : pp);
+}
+
+// Column i of the round's rotation J: alpha e_u + beta e_v.  An index paired
+// with the padding index (n odd) keeps the identity column.
+struct Col {
+  int u, v, k;
+  bool ident, first;
+  double a, b;
+};
+
+__device__ inline Col column_of(int i, int r, int n, int N2, const double* rc, const double* rs) {
+  int k, partner;
+  pair_of(i, r, N2, k, partner);
+  Col c;
+  c.k = k;
+  c.ident = partner >= n;
+  c.first = i < partner;
+  const double cc = rc[k], ss = rs[k];
+  c.u = c.ident ? i : (c.first ? i : partner);
+  c.v = c.ident ? i : (c.first ? partner : i);
+  c.a = c.ident ? 1.0 : (c.first ? cc : ss);
+  c.b = c.ident ? 0.0 : (c.first ? -ss : cc);
+  return c;
+}
+
+// Entry (i, j), i <= j, of J^T G J for the round (G with leading dimension
+// LD).  Every load is issued unconditionally; the case is chosen by selects.
+template <int LD>
+__device__ inline double rotated_entry(int i, int j, int r, int n, int N2, const double* G,
+                                       const double* rc, const double* rs, const double* rt) {
+  const Col ci = column_of(i, r, n, N2, rc, rs);
+  const Col cj = column_of(j, r, n, N2, rc, rs);
+  const double g_uu = G[ci.u * LD + cj.u];
+  const double g_uv = G[ci.u * LD + cj.v];
+  const double g_vu = G[ci.v * LD + cj.u];
+  const double g_vv = G[ci.v * LD + cj.v];
+  const double g_ij = G[i * LD + j];
+  const double dti = rt[ci.k];
+  const double si = rs[ci.k];
+  double gen = ci.a * cj.a * g_uu;
+  gen = fma(ci.a * cj.b, g_uv, gen);
+  gen = fma(ci.b * cj.a, g_vu, gen);
+  gen = fma(ci.b * cj.b, g_vv, gen);
+  const double diag = g_ij + (ci.ident ? 0.0 : (ci.first ? -dti : dti));
+  const bool same_pair = !ci.ident && ci.u == cj.u && ci.v == cj.v;
+  const double paired = si != 0.0 ? 0.0 : g_ij;
+  return i == j ? diag : (same_pair ? paired : gen);
+}
+
+// Rotation of one pair from the entries of G.
+template <typename T>
+__device__ inline void make_rotation(double gpp, double gqq, double gpq, double& c, double& s,
+                                     double& dt) {
+  if (off_diag_large<T>(gpq, gpp, gqq)) {
+    const double d = gqq - gpp;
+    double t = 2.0 * gpq / (fabs(d) + sqrt(fma(d, d, 4.0 * gpq * gpq)));
+    if (d < 0.0) t = -t;
+    c = 1.0 / sqrt(fma(t, t, 1.0));
+    s = t * c;
+    dt = t * gpq;
+  } else {
+    c = 1.0;
+    s = 0.0;
+    dt = 0.0;
+  }
+}
+
+// Dot product over the zero-padded length NMAX with four independent
+// partial sums (fixed trip count, so every load can be in flight at once).
+template <int NMAX, typename F>
+__device__ inline double dot4(F&& term) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < NMAX; k += 4) {
+    s0 = term(k + 0, s0);
+    s1 = term(k + 1, s1);
+    s2 = term(k + 2, s2);
+    s3 = term(k + 3, s3);
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
+template <typename T, int NMAX, int NT>
+__global__ void __launch_bounds__(NT)
+k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
+  constexpr int LD = NMAX + 1;
+  constexpr int MU = (NMAX * (NMAX + 1) / 2 + NT - 1) / NT;  // upper entries per thread
+  constexpr int MF = (NMAX * NMAX + NT - 1) / NT;            // full entries per thread
+  __shared__ double G0s[NMAX * LD], G1s[NMAX * LD];  // two copies of G
+  __shared__ double V0s[NMAX * LD], V1s[NMAX * LD];  // two copies of V
+  __shared__ double rc[2][NMAX / 2], rs[2][NMAX / 2], rt[2][NMAX / 2];
+  __shared__ double w[NMAX];
   __shared__ double scal[kScalars];
   __shared__ int s_go;
 
   const int tid = threadIdx.x;
-  const SolveDesc& d = descs[blockIdx.x];
+  const SolveDesc& d = descs[ids[blockIdx.x]];
   SolveState* st = d.st;
 #ifdef RPCA_TRACE
   int64_t tprev = RPCA_NOW();
@@ -76,15 +208,57 @@ __global__ void __launch_bounds__(kEigThreads) k_eig(const SolveDesc* __restrict
   const int n = d.n;
   const int nb = d.nb;
   const int kd = st->iter;
+  const bool warm = kd > 0;
+  const int nup = n * (n + 1) / 2;
+  const int nfull = n * n;
 
-  // Final level of the streaming pass's reduction: group partials added in
-  // group order, the Gram straight into LDS.
+  // Owned entries: upper-triangle (i <= j, column-packed) and full (row-major).
+  int ui[MU], uj[MU], fr[MF], fc[MF];
+#pragma unroll
+  for (int q = 0; q < MU; ++q) {
+    const int idx = tid + q * NT;
+    int j = 0;
+    if (idx < nup) {
+      while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+    }
+    uj[q] = j;
+    ui[q] = idx < nup ? idx - j * (j + 1) / 2 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < MF; ++q) {
+    const int idx = tid + q * NT;
+    fr[q] = idx < nfull ? idx / n : 0;
+    fc[q] = idx < nfull ? idx - fr[q] * n : 0;
+  }
+
+  // Previous eigenvectors: issue the loads before the reduction.
+  double vpre[MF];
+#pragma unroll
+  for (int q = 0; q < MF; ++q) {
+    vpre[q] = 0.0;
+    if (tid + q * NT < nfull) {
+      vpre[q] = warm ? d.V[fr[q] * nb + fc[q]] : (fr[q] == fc[q] ? 1.0 : 0.0);
+    }
+  }
+
+  // Zero the LDS matrices: entries outside n x n stay zero for the whole
+  // solve step, so fixed-length dot products need no guards.
+  for (int idx = tid; idx < NMAX * LD; idx += NT) {
+    G0s[idx] = 0.0;
+    G1s[idx] = 0.0;
+    V0s[idx] = 0.0;
+    V1s[idx] = 0.0;
+  }
+  if (tid < NMAX) w[tid] = 0.0;
+  __syncthreads();
+
+  // 0. Final level of the streaming pass's reduction, Gram straight into LDS.
   {
     const int nblk = gram_blocks((n + 3) >> 2);
     const int nent = kScalars + nblk * 16;
     constexpr int kChunk = 16;
-    for (int idx = tid; idx < nent; idx += kEigThreads) {
-      double s = 0.0;
+    for (int idx = tid; idx < nent; idx += NT) {
+      double sum = 0.0;
       for (int q0 = 0; q0 < d.groups; q0 += kChunk) {
         const int c = min(kChunk, d.groups - q0);
         double v[kChunk];
@@ -93,10 +267,10 @@ __global__ void __launch_bounds__(kEigThreads) k_eig(const SolveDesc* __restrict
           v[q] = q < c ? d.gpartials[static_cast<size_t>(q0 + q) * d.pstride + idx] : 0.0;
 #pragma unroll
         for (int q = 0; q < kChunk; ++q)
-          if (q < c) s += v[q];
+          if (q < c) sum += v[q];
       }
       if (idx < kScalars) {
-        scal[idx] = s;
+        scal[idx] = sum;
       } else {
         const int g = idx - kScalars;
         const int blk = g >> 4, e = g & 15;
@@ -105,14 +279,18 @@ __global__ void __launch_bounds__(kEigThreads) k_eig(const SolveDesc* __restrict
         const int bi = blk - bj * (bj + 1) / 2;
         const int i = 4 * bi + (e >> 2), j = 4 * bj + (e & 3);
         if (i < n && j < n) {
-          G[i * LD + j] = s;
-          G[j * LD + i] = s;
+          G0s[i * LD + j] = sum;
+          G0s[j * LD + i] = sum;
         }
       }
     }
   }
+#pragma unroll
+  for (int q = 0; q < MF; ++q)
+    if (tid + q * NT < nfull) V0s[fr[q] * LD + fc[q]] = vpre[q];
   __syncthreads();
 
+  // 1. Control.
   if (tid == 0) {
     int go = 0;
     if (kd == 0) {
@@ -162,257 +340,182 @@ __global__ void __launch_bounds__(kEigThreads) k_eig(const SolveDesc* __restrict
   __syncthreads();
   if (!s_go) return;
   EIG_MARK(0);
-
-  const bool warm = kd > 0;
   const double tau = st->tau;
+  int cur = 0;  // which copy (0 or 1) holds the current G and V
 
-  // Upper-triangle entries owned by this thread (column-packed order).
-  const int nup = n * (n + 1) / 2;
-  int ui[kMaxUpper], uj[kMaxUpper];
-#pragma unroll
-  for (int q = 0; q < kMaxUpper; ++q) {
-    const int idx = tid + q * kEigThreads;
-    int j = 0;
-    if (idx < nup) {
+  // 2. Warm start.  Each product goes straight into a buffer that is not one
+  // of its operands; a barrier separates the products.  G~ and V1 end in copy 1.
+  if (warm) {
+    for (int idx = tid; idx < nup; idx += NT) {  // C = V^T V  -> G1s
+      int j = 0;
       while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+      const int i = idx - j * (j + 1) / 2;
+      const double c = dot4<NMAX>([&](int k, double acc) { return fma(V0s[k * LD + i], V0s[k * LD + j], acc); });
+      G1s[i * LD + j] = c;
+      G1s[j * LD + i] = c;
     }
-    uj[q] = j;
-    ui[q] = idx < nup ? idx - j * (j + 1) / 2 : 0;
+    __syncthreads();
+    for (int idx = tid; idx < nfull; idx += NT) {  // V1 = 1.5 V - 0.5 V C  -> V1s
+      const int i = idx / n, j = idx - (idx / n) * n;
+      const double vc = dot4<NMAX>([&](int k, double acc) { return fma(V0s[i * LD + k], G1s[k * LD + j], acc); });
+      V1s[i * LD + j] = fma(-0.5, vc, 1.5 * V0s[i * LD + j]);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nfull; idx += NT) {  // W = G V1  -> V0s (V is dead)
+      const int i = idx / n, j = idx - (idx / n) * n;
+      V0s[i * LD + j] = dot4<NMAX>([&](int k, double acc) { return fma(G0s[i * LD + k], V1s[k * LD + j], acc); });
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nup; idx += NT) {  // G~ = V1^T W  -> G1s (C is dead)
+      int j = 0;
+      while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+      const int i = idx - j * (j + 1) / 2;
+      const double g = dot4<NMAX>([&](int k, double acc) { return fma(V1s[k * LD + i], V0s[k * LD + j], acc); });
+      G1s[i * LD + j] = g;
+      G1s[j * LD + i] = g;
+    }
+    cur = 1;
+    __syncthreads();
   }
-  const int nfull = n * n;
-
-  for (int idx = tid; idx < nfull; idx += kEigThreads) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    V[i * LD + j] = warm ? d.V[i * nb + j] : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
   EIG_MARK(1);
 
-  if (warm) {
-    // Newton-Schulz: C = V^T V, then V <- V (1.5 I - 0.5 C).
-    double cu[kMaxUpper];
+  // 3. Jacobi sweeps.
+  const int N2 = n + (n & 1);
+  const int M = N2 - 1;
+  const int NP = N2 / 2;
+  int sweeps = 0;
+  // One round: read copy SRC, write J^T G J and V J into the other copy, and
+  // (threads tid < NP) the rotations of round r+1.
+  auto round = [&](auto src_tag, int r) {
+    constexpr int SRC = decltype(src_tag)::value;
+    const double* Gc = SRC ? G1s : G0s;
+    double* Gn = SRC ? G0s : G1s;
+    const double* Vc = SRC ? V1s : V0s;
+    double* Vn = SRC ? V0s : V1s;
+    const int rb = r & 1;
 #pragma unroll
-    for (int q = 0; q < kMaxUpper; ++q) {
-      cu[q] = 0.0;
-      if (tid + q * kEigThreads < nup) {
+    for (int q = 0; q < MU; ++q) {
+      if (tid + q * NT < nup) {  // slots past n(n+1)/2 are skipped by whole waves
+        const double v = rotated_entry<LD>(ui[q], uj[q], r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
+        Gn[ui[q] * LD + uj[q]] = v;
+        Gn[uj[q] * LD + ui[q]] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MF; ++q) {
+      if (tid + q * NT < nfull) {
+        const Col cj = column_of(fc[q], r, n, N2, rc[rb], rs[rb]);
+        const int i = fr[q];
+        Vn[i * LD + fc[q]] = fma(cj.a, Vc[i * LD + cj.u], cj.b * Vc[i * LD + cj.v]);
+      }
+    }
+    // The next round's rotations are computed by the last wavefront, which
+    // owns the fewest matrix entries.
+    const int kp = tid - (NT - 64);
+    if (r + 1 < M && kp >= 0 && kp < NP) {
+      int p, q;
+      pair_indices(r + 1, kp, N2, p, q);
+      double c = 1.0, s = 0.0, dt = 0.0;
+      if (q < n) {
+        const double gpp = rotated_entry<LD>(p, p, r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
+        const double gqq = rotated_entry<LD>(q, q, r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
+        const double gpq = rotated_entry<LD>(p, q, r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
+        make_rotation<T>(gpp, gqq, gpq, c, s, dt);
+      }
+      rc[rb ^ 1][kp] = c;
+      rs[rb ^ 1][kp] = s;
+      rt[rb ^ 1][kp] = dt;
+    }
+    __syncthreads();
+  };
+  for (; sweeps < kMaxSweeps && n > 1; ++sweeps) {
+    // Convergence test of the current G, and the rotations of round 0.
+    const double* G = cur ? G1s : G0s;
+    int need = 0;
+#pragma unroll
+    for (int q = 0; q < MU; ++q) {
+      if (tid + q * NT < nup && ui[q] < uj[q]) {
         const int i = ui[q], j = uj[q];
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s = fma(V[k * LD + i], V[k * LD + j], s);
-        cu[q] = s;
+        if (off_diag_large<T>(G[i * LD + j], G[i * LD + i], G[j * LD + j])) need = 1;
       }
     }
-#pragma unroll
-    for (int q = 0; q < kMaxUpper; ++q) {
-      if (tid + q * kEigThreads < nup) {
-        C[ui[q] * LD + uj[q]] = cu[q];
-        C[uj[q] * LD + ui[q]] = cu[q];
-      }
+    if (tid < NP) {
+      int p, q;
+      pair_indices(0, tid, N2, p, q);
+      double c = 1.0, s = 0.0, dt = 0.0;
+      if (q < n) make_rotation<T>(G[p * LD + p], G[q * LD + q], G[p * LD + q], c, s, dt);
+      rc[0][tid] = c;
+      rs[0][tid] = s;
+      rt[0][tid] = dt;
     }
-    __syncthreads();
-    double vt[kMaxFull];
-#pragma unroll
-    for (int q = 0; q < kMaxFull; ++q) {
-      const int idx = tid + q * kEigThreads;
-      vt[q] = 0.0;
-      if (idx < nfull) {
-        const int i = idx / n, j = idx - (idx / n) * n;
-        double s = 1.5 * V[i * LD + j];
-        for (int k = 0; k < n; ++k) s = fma(-0.5 * V[i * LD + k], C[k * LD + j], s);
-        vt[q] = s;
-      }
+    if (!__syncthreads_or(need)) break;
+    for (int r = 0; r < M; ++r) {
+      if (cur) round(std::integral_constant<int, 1>{}, r);
+      else round(std::integral_constant<int, 0>{}, r);
+      cur ^= 1;
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kMaxFull; ++q) {
-      const int idx = tid + q * kEigThreads;
-      if (idx < nfull) {
-        const int i = idx / n, j = idx - (idx / n) * n;
-        V[i * LD + j] = vt[q];
-      }
-    }
-    __syncthreads();
-
-    double tmp[kMaxFull];
-#pragma unroll
-    for (int q = 0; q < kMaxFull; ++q) {
-      const int idx = tid + q * kEigThreads;
-      tmp[q] = 0.0;
-      if (idx < nfull) {
-        const int i = idx / n, j = idx - (idx / n) * n;
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s = fma(G[i * LD + k], V[k * LD + j], s);
-        tmp[q] = s;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kMaxFull; ++q) {
-      const int idx = tid + q * kEigThreads;
-      if (idx < nfull) {
-        const int i = idx / n, j = idx - (idx / n) * n;
-        G[i * LD + j] = tmp[q];  // G now holds W = G V
-      }
-    }
-    __syncthreads();
-    double tu[kMaxUpper];
-#pragma unroll
-    for (int q = 0; q < kMaxUpper; ++q) {
-      tu[q] = 0.0;
-      if (tid + q * kEigThreads < nup) {
-        const int i = ui[q], j = uj[q];
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s = fma(V[k * LD + i], G[k * LD + j], s);
-        tu[q] = s;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kMaxUpper; ++q) {
-      if (tid + q * kEigThreads < nup) {
-        G[ui[q] * LD + uj[q]] = tu[q];
-        G[uj[q] * LD + ui[q]] = tu[q];
-      }
-    }
-    __syncthreads();
   }
   EIG_MARK(2);
 
-  const int N2 = n + (n & 1);
-  int sweeps = 0;
-  for (; sweeps < kMaxSweeps && n > 1; ++sweeps) {
-    int need = 0;
-#pragma unroll
-    for (int q = 0; q < kMaxUpper; ++q) {
-      if (tid + q * kEigThreads < nup && ui[q] < uj[q]) {
-        const int i = ui[q], j = uj[q];
-        if (off_diag_large(G[i * LD + j], G[i * LD + i], G[j * LD + j])) need = 1;
-      }
-    }
-    if (!__syncthreads_or(need)) break;
-    for (int r = 0; r < N2 - 1; ++r) {
-      if (tid < N2 / 2) {
-        int a, b;
-        if (tid == 0) {
-          a = N2 - 1;
-          b = r;
-        } else {
-          a = (r + tid) % (N2 - 1);
-          b = (r - tid + N2 - 1) % (N2 - 1);
-        }
-        const int p = a < b ? a : b;
-        const int q = a < b ? b : a;
-        bool rot = false;
-        if (q < n) {
-          const double gpp = G[p * LD + p], gqq = G[q * LD + q], gpq = G[p * LD + q];
-          if (off_diag_large(gpq, gpp, gqq)) {
-            const double th = (gqq - gpp) / (2.0 * gpq);
-            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-            const double c = 1.0 / sqrt(1.0 + t * t);
-            const double s = t * c;
-            uu[p] = p; vv[p] = q; al[p] = c; be[p] = -s; dg[p] = -t * gpq; partner[p] = q;
-            uu[q] = p; vv[q] = q; al[q] = s; be[q] = c;  dg[q] = t * gpq;  partner[q] = p;
-            rot = true;
-          }
-        }
-        if (!rot) {
-          if (p < n) { uu[p] = p; vv[p] = p; al[p] = 1.0; be[p] = 0.0; dg[p] = 0.0; partner[p] = -1; }
-          if (q < n) { uu[q] = q; vv[q] = q; al[q] = 1.0; be[q] = 0.0; dg[q] = 0.0; partner[q] = -1; }
-        }
-      }
-      __syncthreads();
-      double gn[kMaxUpper], vn[kMaxFull];
-#pragma unroll
-      for (int q = 0; q < kMaxUpper; ++q) {
-        gn[q] = 0.0;
-        if (tid + q * kEigThreads < nup) {
-          const int i = ui[q], j = uj[q];
-          if (i == j) {
-            gn[q] = G[i * LD + i] + dg[i];
-          } else if (partner[i] == j) {
-            gn[q] = 0.0;
-          } else {
-            const int ua = uu[i], va = vv[i], ub = uu[j], vb = vv[j];
-            const double ai = al[i], bi = be[i], aj = al[j], bj = be[j];
-            double s = ai * aj * G[ua * LD + ub];
-            s = fma(ai * bj, G[ua * LD + vb], s);
-            s = fma(bi * aj, G[va * LD + ub], s);
-            s = fma(bi * bj, G[va * LD + vb], s);
-            gn[q] = s;
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kMaxFull; ++q) {
-        vn[q] = 0.0;
-        const int idx = tid + q * kEigThreads;
-        if (idx < nfull) {
-          const int rr = idx / n, j = idx - (idx / n) * n;
-          vn[q] = fma(al[j], V[rr * LD + uu[j]], be[j] * V[rr * LD + vv[j]]);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < kMaxUpper; ++q) {
-        if (tid + q * kEigThreads < nup) {
-          G[ui[q] * LD + uj[q]] = gn[q];
-          G[uj[q] * LD + ui[q]] = gn[q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kMaxFull; ++q) {
-        const int idx = tid + q * kEigThreads;
-        if (idx < nfull) {
-          const int rr = idx / n, j = idx - (idx / n) * n;
-          V[rr * LD + j] = vn[q];
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  EIG_MARK(3);
-  // SVT weights from the eigenvalues sigma_i^2 of A^T A.
+  // 4. SVT weights and the projector P = V diag(w) V^T (exactly symmetric).
+  const double* Gf = cur ? G1s : G0s;
+  const double* Vf = cur ? V1s : V0s;
   if (tid < n) {
-    const double sg = sqrt(fmax(G[tid * LD + tid], 0.0));
+    const double sg = sqrt(fmax(Gf[tid * LD + tid], 0.0));
     w[tid] = sg > tau ? (sg - tau) / sg : 0.0;
   }
   __syncthreads();
-
-  T* __restrict__ Pd = static_cast<T*>(d.P);
-  for (int idx = tid; idx < nb * nb; idx += kEigThreads) {
-    const int i = idx / nb, j = idx - (idx / nb) * nb;
+  const gptr<T> Pd = as_global<T>(d.P);
+  const int nbup = nb * (nb + 1) / 2;
+  for (int idx = tid; idx < nbup; idx += NT) {
+    int j = 0;
+    while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+    const int i = idx - j * (j + 1) / 2;
     double s = 0.0;
-    if (i < n && j < n) {
-      for (int k = 0; k < n; ++k) {
-        const double wk = w[k];
-        if (wk != 0.0) s = fma(V[i * LD + k] * wk, V[j * LD + k], s);
-      }
+    if (j < n) {
+      s = dot4<NMAX>([&](int k, double acc) { return fma(Vf[i * LD + k] * w[k], Vf[j * LD + k], acc); });
     }
-    Pd[idx] = static_cast<T>(s);
+    Pd[i * nb + j] = static_cast<T>(s);
+    Pd[j * nb + i] = static_cast<T>(s);
   }
-  for (int idx = tid; idx < nfull; idx += kEigThreads) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    d.V[i * nb + j] = V[i * LD + j];
-  }
-  EIG_MARK(4);
+#pragma unroll
+  for (int q = 0; q < MF; ++q)
+    if (tid + q * NT < nfull) d.V[fr[q] * nb + fc[q]] = Vf[fr[q] * LD + fc[q]];
+  EIG_MARK(3);
   if (tid == 0) {
     int rank = 0;
     for (int k = 0; k < n; ++k) rank += w[k] != 0.0 ? 1 : 0;
     st->rank = rank;
     st->sweeps = sweeps;
     st->sweeps_total += sweeps;
-    st->iter = st->iter + 1;
+    st->iter = kd + 1;
   }
+#undef EIG_MARK
 }
 
 }  // namespace
 
-hipError_t launch_eig(int dtype, int grid, hipStream_t stream, const SolveDesc* descs) {
+int eig_class(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= kEigMaxN ? 64 : 0)); }
+
+hipError_t launch_eig(int dtype, int ncls, int grid, hipStream_t stream, const SolveDesc* descs,
+                      const int32_t* ids) {
   if (grid <= 0) return hipSuccess;
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_eig<double>, dim3(grid), dim3(kEigThreads), 0, stream, descs);
-  else
-    hipLaunchKernelGGL(k_eig<float>, dim3(grid), dim3(kEigThreads), 0, stream, descs);
+  const dim3 g(grid), b(kEigThreads);
+#define RPCA_EIG_CASE(N)                                                                  \
+  case N:                                                                                 \
+    if (dtype == 0)                                                                       \
+      hipLaunchKernelGGL((k_eig<double, N, kEigThreads>), g, b, 0, stream, descs, ids);   \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_eig<float, N, kEigThreads>), g, b, 0, stream, descs, ids);    \
+    break;
+  switch (ncls) {
+    RPCA_EIG_CASE(16)
+    RPCA_EIG_CASE(32)
+    RPCA_EIG_CASE(64)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef RPCA_EIG_CASE
   return hipGetLastError();
 }
 

@@ -2,11 +2,12 @@
 //
 // A call (one solve or a batch) is laid out as follows:
 //   * one stream-ordered device allocation holds the control block (solve
-//     descriptors, the work-item table, solve states, arrival counters) and
+//     descriptors, the work-item and group tables, solve states) and
 //     every solve's iterate buffers, reduction partials, Gram, projector and
 //     eigenvectors;
 //   * the init pass runs once per frame class, then iterations are enqueued
-//     in chunks of [eigensolve for all solves, update pass per frame class];
+//     in chunks of [eigensolve per eigensolver class, update pass per frame
+//     class, group reduction];
 //     a solve that has finished makes its later launches exit at once, so the
 //     host only reads the solve states back between chunks;
 //   * the finalize pass writes L and S, the states are read back, and the
@@ -19,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "rpca.h"
@@ -148,25 +150,23 @@ void trace_report(const SolveState& st, const void* dtrace, int slots, hipStream
     return;
   const double it = st.iter > 0 ? st.iter : 1;
   std::fprintf(stderr,
-               "[trace] eig us/iter: control %.2f load %.2f warm %.2f jacobi %.2f project %.2f "
+               "[trace] eig us/iter: reduce+control %.2f warm %.2f jacobi %.2f project %.2f "
                "(sweeps/iter %.2f)\n",
                st.trace[0] * 0.01 / it, st.trace[1] * 0.01 / it, st.trace[2] * 0.01 / it,
-               st.trace[3] * 0.01 / it, st.trace[4] * 0.01 / it, st.sweeps_total / it);
-  int64_t b0 = INT64_MAX, b1 = 0, e1 = 0, e2 = 0, e3 = 0;
+               st.trace[3] * 0.01 / it, st.sweeps_total / it);
+  int64_t b0 = INT64_MAX, b1 = 0, e1 = 0, e2 = 0;
   double sum_tiles = 0;
   for (int s = 0; s < slots; ++s) {
     b0 = std::min(b0, t[s * 4 + 0]);
     b1 = std::max(b1, t[s * 4 + 0]);
     e1 = std::max(e1, t[s * 4 + 1]);
     e2 = std::max(e2, t[s * 4 + 2]);
-    e3 = std::max(e3, t[s * 4 + 3]);
     sum_tiles += static_cast<double>(t[s * 4 + 1] - t[s * 4 + 0]);
   }
   std::fprintf(stderr,
-               "[trace] update us: last WG start %.2f, tiles done %.2f, partials %.2f, "
-               "reduced %.2f; mean WG tile time %.2f\n",
-               (b1 - b0) * 0.01, (e1 - b0) * 0.01, (e2 - b0) * 0.01, (e3 - b0) * 0.01,
-               sum_tiles / slots * 0.01);
+               "[trace] update us: last WG start %.2f, tiles done %.2f, partials %.2f; "
+               "mean WG tile time %.2f\n",
+               (b1 - b0) * 0.01, (e1 - b0) * 0.01, (e2 - b0) * 0.01, sum_tiles / slots * 0.01);
 }
 #endif
 
@@ -227,18 +227,29 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
     c.item_cnt = static_cast<int>(items.size()) - c.item_off;
   }
 
-  // Control block: descs | items | states | counters.
-  size_t ncnt = 0;
-  std::vector<size_t> cnt_off(count);
-  for (int i = 0; i < count; ++i) {
-    cnt_off[i] = ncnt;
-    ncnt += static_cast<size_t>(geo[i].groups) + 1;
+  // Eigensolver classes and their solve-id lists.
+  std::vector<int32_t> eig_ids;
+  std::vector<std::pair<int, std::pair<int, int>>> eig_runs;  // (class, (offset, count))
+  for (int cls : {16, 32, 64}) {
+    const int off = static_cast<int>(eig_ids.size());
+    for (int i = 0; i < count; ++i)
+      if (eig_class(static_cast<int>(probs[i].n)) == cls) eig_ids.push_back(i);
+    const int cnt = static_cast<int>(eig_ids.size()) - off;
+    if (cnt > 0) eig_runs.push_back({cls, {off, cnt}});
   }
+
+  // Group items of the reduction launch.
+  std::vector<GroupItem> gitems;
+  for (int i = 0; i < count; ++i)
+    for (int g = 0; g < geo[i].groups; ++g) gitems.push_back(GroupItem{i, g});
+
+  // Control block: descs | items | group items | eig ids | states.
   const size_t off_desc = 0;
   const size_t off_items = al256(off_desc + sizeof(SolveDesc) * count);
-  const size_t off_state = al256(off_items + sizeof(WorkItem) * items.size());
-  const size_t off_cnt = al256(off_state + sizeof(SolveState) * count);
-  const size_t ctrl_bytes = al256(off_cnt + sizeof(uint32_t) * ncnt);
+  const size_t off_gitems = al256(off_items + sizeof(WorkItem) * items.size());
+  const size_t off_ids = al256(off_gitems + sizeof(GroupItem) * gitems.size());
+  const size_t off_state = al256(off_ids + sizeof(int32_t) * eig_ids.size());
+  const size_t ctrl_bytes = al256(off_state + sizeof(SolveState) * count);
   size_t total = ctrl_bytes;
   std::vector<size_t> base(count);
   for (int i = 0; i < count; ++i) {
@@ -284,7 +295,6 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   {
     SolveDesc* dh = reinterpret_cast<SolveDesc*>(ctrl_h.data() + off_desc);
     SolveState* sd = reinterpret_cast<SolveState*>(arena + off_state);
-    uint32_t* cd = reinterpret_cast<uint32_t*>(arena + off_cnt);
     for (int i = 0; i < count; ++i) {
       const rpca_problem& p = probs[i];
       char* b = arena + base[i];
@@ -302,7 +312,6 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
       d.P = b + big[i].P;
       d.V = reinterpret_cast<double*>(b + big[i].V);
       d.st = sd + i;
-      d.counters = cd + cnt_off[i];
 #ifdef RPCA_TRACE
       d.wgtrace = reinterpret_cast<int64_t*>(b + big[i].trace);
 #endif
@@ -320,12 +329,17 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
       d.tol = p.tol;
     }
     std::memcpy(ctrl_h.data() + off_items, items.data(), sizeof(WorkItem) * items.size());
-    // states and counters start at zero (ctrl_h is zero-filled)
+    std::memcpy(ctrl_h.data() + off_gitems, gitems.data(), sizeof(GroupItem) * gitems.size());
+    std::memcpy(ctrl_h.data() + off_ids, eig_ids.data(), sizeof(int32_t) * eig_ids.size());
+    // states start at zero (ctrl_h is zero-filled)
   }
 
   {
     const SolveDesc* descs = reinterpret_cast<const SolveDesc*>(arena + off_desc);
     const WorkItem* items_d = reinterpret_cast<const WorkItem*>(arena + off_items);
+    const int32_t* ids_d = reinterpret_cast<const int32_t*>(arena + off_ids);
+    const GroupItem* gitems_d = reinterpret_cast<const GroupItem*>(arena + off_gitems);
+    const int ngroups = static_cast<int>(gitems.size());
     auto launch_class = [&](const ClassRun& c, int mode) -> hipError_t {
       if (dtype == RPCA_F32)
         return launch_stream_f32(c.nb, mode, c.item_cnt, stream, descs, items_d + c.item_off);
@@ -352,6 +366,7 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
       CK(launch_class(classes[c], kModeInit));
       ev_end();
     }
+    CK(launch_reduce(ngroups, stream, descs, gitems_d));
 
     int maxit_all = 0;
     for (int i = 0; i < count; ++i) maxit_all = std::max(maxit_all, probs[i].maxit);
@@ -361,14 +376,18 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
     while (!all_done) {
       for (int c = 0; c < chunk; ++c) {
         ++launched;
-        ev_begin(1, launched, -1);
-        CK(launch_eig(dtype == RPCA_F32 ? 1 : 0, count, stream, descs));
-        ev_end();
+        for (const auto& er : eig_runs) {
+          ev_begin(1, launched, -1);
+          CK(launch_eig(dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, stream, descs,
+                        ids_d + er.second.first));
+          ev_end();
+        }
         for (size_t q = 0; q < classes.size(); ++q) {
           ev_begin(2, launched, static_cast<int>(q));
           CK(launch_class(classes[q], kModeUpdate));
           ev_end();
         }
+        CK(launch_reduce(ngroups, stream, descs, gitems_d));
       }
       CK(hipMemcpyAsync(st_h, arena + off_state, sizeof(SolveState) * count,
                         hipMemcpyDeviceToHost, stream));
@@ -506,7 +525,7 @@ size_t rpca_footprint_bytes(int64_t m, int64_t n, int32_t dtype) {
   if (!geometry(m, n, dtype, g)) return 0;
   const Big b = big_layout(m, n, g);
   return b.total + al256(sizeof(SolveDesc)) + al256(sizeof(SolveState)) +
-         al256(sizeof(uint32_t) * (g.groups + 1)) + al256(sizeof(WorkItem) * g.slots);
+         al256(sizeof(GroupItem) * g.groups) + al256(sizeof(WorkItem) * g.slots) + 256;
 }
 
 const char* rpca_strerror(int code) {

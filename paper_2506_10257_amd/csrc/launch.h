@@ -17,6 +17,13 @@ hipError_t launch_stream_f32(int nb, int mode, int grid, hipStream_t stream,
                              const SolveDesc* descs, const WorkItem* items);
 hipError_t launch_stream_f64(int nb, int mode, int grid, hipStream_t stream,
                              const SolveDesc* descs, const WorkItem* items);
-hipError_t launch_eig(int dtype, int grid, hipStream_t stream, const SolveDesc* descs);
+hipError_t launch_reduce(int grid, hipStream_t stream, const SolveDesc* descs,
+                         const GroupItem* items);
+
+// Eigensolver classes 16, 32 and 64: the largest n each handles (256
+// threads each).  ids lists the solves (indices into descs) of the launch.
+int eig_class(int n);
+hipError_t launch_eig(int dtype, int ncls, int grid, hipStream_t stream, const SolveDesc* descs,
+                      const int32_t* ids);
 
 }  // namespace rpca

@@ -24,11 +24,12 @@
 // k_finalize            : L = A_k P_k for the last iterate (same arithmetic as
 //                         the rebuild above) and S_k, into the caller's buffers.
 //
-// Reductions never use floating-point atomics.  Each workgroup writes its
-// partial sums to a fixed slot; the last workgroup to arrive in a group of
-// kGroup slots adds them in slot order, and the eigensolve kernel adds the
-// group sums in group order.  The result depends only on the solve's own
-// shape, so it is bitwise the same whether the solve runs alone or in a batch.
+// Reductions never use floating-point atomics, and the streaming kernels use
+// no cross-workgroup synchronisation at all: each workgroup writes its partial
+// sums to a fixed slot; the next launch (k_reduce_groups) adds each group of
+// kGroup slots in slot order, and the eigensolve kernel adds the group sums in
+// group order.  Kernel boundaries order the steps.  The result depends only on
+// the solve's own shape, so it is bitwise the same alone or in a batch.
 #pragma once
 
 #include "common.h"
@@ -53,40 +54,6 @@ __device__ inline double clamp_sym(double v, double g) { return fmin(fmax(v, -g)
 __device__ inline bool finite_val(float v) { return __builtin_isfinite(v); }
 __device__ inline bool finite_val(double v) { return __builtin_isfinite(v); }
 
-// First level of the fixed-order reduction.  Every workgroup writes its own
-// partial slot; the last workgroup to arrive in a group of kGroup consecutive
-// slots adds the group's slots in slot order into the group partial.  The
-// eigensolve kernel of the next step adds the group partials in group order.
-__device__ inline void reduce_group(const SolveDesc& d, int slot, int nent, int* s_flag) {
-  const int tid = threadIdx.x;
-  __threadfence();
-  __syncthreads();
-  const int g = slot / kGroup;
-  const int lo = g * kGroup;
-  const int cnt = min(lo + kGroup, d.slots) - lo;
-  if (tid == 0) {
-    const uint32_t prev = __hip_atomic_fetch_add(&d.counters[g], 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    *s_flag = (prev == static_cast<uint32_t>(cnt - 1)) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!*s_flag) return;
-  __threadfence();
-  const double* src = d.partials + static_cast<size_t>(lo) * d.pstride;
-  for (int idx = tid; idx < nent; idx += blockDim.x) {
-    // all loads of the group in flight at once, then the sum in slot order
-    double v[kGroup];
-#pragma unroll
-    for (int q = 0; q < kGroup; ++q) v[q] = q < cnt ? src[static_cast<size_t>(q) * d.pstride + idx] : 0.0;
-    double s = v[0];
-#pragma unroll
-    for (int q = 1; q < kGroup; ++q)
-      if (q < cnt) s += v[q];
-    d.gpartials[static_cast<size_t>(g) * d.pstride + idx] = s;
-  }
-  if (tid == 0) d.counters[g] = 0u;
-}
-
 template <typename T, int NB, bool INIT>
 __global__ void __launch_bounds__(kThreads)
 k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
@@ -97,7 +64,6 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   constexpr size_t kSmem = kTileBytes > kRedBytes ? kTileBytes : kRedBytes;
   __shared__ __align__(16) unsigned char smem[kSmem];
   __shared__ double wred[kThreads / 64][kScalars];
-  __shared__ int s_flag;
   T* tileA = reinterpret_cast<T*>(smem);
   double* red = reinterpret_cast<double*>(smem);
 
@@ -179,10 +145,11 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
       for (int j = 0; j < NB4; ++j) {
         T apj = 0;
         if (j < NB && j < n) {
-          // Eq. 4 rebuild: l = sum_i a_i P_ij (P is zero outside n x n).
+          // Eq. 4 rebuild: l = sum_i a_i P_ij (P is zero outside n x n and
+          // exactly symmetric; row j of P is contiguous for scalar loads).
           T l = 0;
 #pragma unroll
-          for (int i = 0; i < NB; ++i) l = fma(a[i], P[i * NB + j], l);
+          for (int i = 0; i < NB; ++i) l = fma(a[i], P[j * NB + i], l);
           const T tt = fma(y[j], imu, x[j]) - l;          // X - L + Y/mu
           const T sn = tt - clamp_sym(tt, gam);            // Eq. 5 shrink
           const T z = (x[j] - l) - sn;                     // X - L - S
@@ -260,10 +227,6 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
 #else
   (void)t_begin;
 #endif
-  reduce_group(d, wi.slot, kScalars + nblk * 16, &s_flag);
-#ifdef RPCA_TRACE
-  if (tid == 0 && d.wgtrace) d.wgtrace[wi.slot * 4 + 3] = RPCA_NOW();
-#endif
 }
 
 template <typename T, int NB>
@@ -319,7 +282,7 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
       if (j < n) {
         T l = 0;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) l = fma(a[i], P[i * NB + j], l);
+        for (int i = 0; i < NB; ++i) l = fma(a[i], P[j * NB + i], l);
         const size_t col = static_cast<size_t>(j) * m;
         (L + col)[p] = l;
         (So + col)[p] = (Sk + col)[p];
