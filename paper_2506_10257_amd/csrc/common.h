@@ -54,8 +54,8 @@ struct SolveDesc {
   int64_t* wgtrace;       // per-slot timestamps (trace builds only, else null)
   int64_t m;
   int32_t n, nb;          // frames and the compiled frame class (n <= nb)
-  int32_t tiles, tps;     // ceil(m / kTile); tiles per slot
-  int32_t slots, groups;  // ceil(tiles / tps); ceil(slots / kGroup)
+  int32_t tiles, tps;     // ceil(m / kTile); tiles per slot (always 1)
+  int32_t slots, groups;  // partial slots (= tiles); ceil(slots / kGroup)
   int32_t pstride;        // doubles per partial slot
   int32_t maxit;
   double lam_in, mu_in, tol;
@@ -94,7 +94,7 @@ __device__ inline cptr<T> as_const(const void* p) {
 
 struct WorkItem {
   int32_t solve;   // index into the SolveDesc array of the launch
-  int32_t slot;    // which tiles: [slot * tps, min((slot + 1) * tps, tiles))
+  int32_t slot;    // which tile: rows [slot * kTile, (slot + 1) * kTile)
 };
 
 struct GroupItem {

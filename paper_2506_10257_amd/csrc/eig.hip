@@ -20,8 +20,8 @@
 //      (each index meets every other once per sweep, n/2 disjoint pairs per
 //      round).  G and V are double-buffered: a round reads one copy and
 //      writes J^T G J and V J into the other, and the threads that own the
-//      next round's pairs compute that round's rotations in the same phase,
-//      so a round costs one barrier;
+//      next round's pairs compute that round's rotations (and the column
+//      table of its J) in the same phase, so a round costs one barrier;
 //   4. w from the eigenvalues, P = V diag(w) V^T in the storage precision.
 //
 // The rotation of a pair is the symmetric 2x2 Schur decomposition with the
@@ -76,67 +76,62 @@ __device__ inline void pair_indices(int r, int k, int N2, int& p, int& q) {
   q = a < b ? b : a;
 }
 
-// Pair number and partner of index i in round r (branch-free).
-__device__ inline void pair_of(int i, int r, int N2, int& k, int& partner) {
-  const int M = N2 - 1;
-  int d1 = i - r;
-  d1 += d1 < 0 ? M : 0;
-  const bool low = d1 < (N2 >> 1);
-  const int kk = low ? d1 : M - d1;
-  int pp = low ? r - d1 : r + kk;
-  pp += pp < 0 ? M : 0;
-  pp -= pp >= M ? M : 0;
-  const bool last = i == N2 - 1;
-  const bool isr = i == r;
-  k = (last || isr) ? 0 : kk;
-  partner = last ? r : (isr ? N2 - 1 : pp);
+// Per-round column table of J, written by the threads that compute the
+// round's rotations: for index i, column i of J is a_i e_u + b_i e_v with
+// (u, v) the pair containing i, packed as u | v << 8 | rotated << 16, and
+// dg_i the exact shift of the diagonal entry g_ii (-t g_pq for p, +t g_pq
+// for q).  An index paired with the padding index gets the identity column.
+__device__ inline void set_pair_columns(int p, int q, int n, double c, double s, double dt,
+                                        int* cu, double* ca, double* cb, double* cd) {
+  if (q >= n) {
+    cu[p] = p | (p << 8);
+    ca[p] = 1.0;
+    cb[p] = 0.0;
+    cd[p] = 0.0;
+    return;
+  }
+  const int packed = p | (q << 8) | (s != 0.0 ? (1 << 16) : 0);
+  cu[p] = packed;
+  ca[p] = c;
+  cb[p] = -s;
+  cd[p] = -dt;
+  cu[q] = packed;
+  ca[q] = s;
+  cb[q] = c;
+  cd[q] = dt;
 }
 
-// Column i of the round's rotation J: alpha e_u + beta e_v.  An index paired
-// with the padding index (n odd) keeps the identity column.
-struct Col {
-  int u, v, k;
-  bool ident, first;
-  double a, b;
-};
-
-__device__ inline Col column_of(int i, int r, int n, int N2, const double* rc, const double* rs) {
-  int k, partner;
-  pair_of(i, r, N2, k, partner);
-  Col c;
-  c.k = k;
-  c.ident = partner >= n;
-  c.first = i < partner;
-  const double cc = rc[k], ss = rs[k];
-  c.u = c.ident ? i : (c.first ? i : partner);
-  c.v = c.ident ? i : (c.first ? partner : i);
-  c.a = c.ident ? 1.0 : (c.first ? cc : ss);
-  c.b = c.ident ? 0.0 : (c.first ? -ss : cc);
-  return c;
-}
-
-// Entry (i, j), i <= j, of J^T G J for the round (G with leading dimension
-// LD).  Every load is issued unconditionally; the case is chosen by selects.
+// Entry (i, j) of J^T G J from the column table (G with leading dimension LD).
 template <int LD>
-__device__ inline double rotated_entry(int i, int j, int r, int n, int N2, const double* G,
-                                       const double* rc, const double* rs, const double* rt) {
-  const Col ci = column_of(i, r, n, N2, rc, rs);
-  const Col cj = column_of(j, r, n, N2, rc, rs);
-  const double g_uu = G[ci.u * LD + cj.u];
-  const double g_uv = G[ci.u * LD + cj.v];
-  const double g_vu = G[ci.v * LD + cj.u];
-  const double g_vv = G[ci.v * LD + cj.v];
-  const double g_ij = G[i * LD + j];
-  const double dti = rt[ci.k];
-  const double si = rs[ci.k];
-  double gen = ci.a * cj.a * g_uu;
-  gen = fma(ci.a * cj.b, g_uv, gen);
-  gen = fma(ci.b * cj.a, g_vu, gen);
-  gen = fma(ci.b * cj.b, g_vv, gen);
-  const double diag = g_ij + (ci.ident ? 0.0 : (ci.first ? -dti : dti));
-  const bool same_pair = !ci.ident && ci.u == cj.u && ci.v == cj.v;
-  const double paired = si != 0.0 ? 0.0 : g_ij;
-  return i == j ? diag : (same_pair ? paired : gen);
+__device__ inline double rotated_entry(int i, int j, const double* G, const int* cu,
+                                       const double* ca, const double* cb, const double* cd) {
+  const int pi = cu[i], pj = cu[j];
+  const int ui = pi & 0xff, vi = (pi >> 8) & 0xff;
+  const int uj = pj & 0xff, vj = (pj >> 8) & 0xff;
+  const double ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
+  double gen = ai * aj * G[ui * LD + uj];
+  gen = fma(ai * bj, G[ui * LD + vj], gen);
+  gen = fma(bi * aj, G[vi * LD + uj], gen);
+  gen = fma(bi * bj, G[vi * LD + vj], gen);
+  const double diag = G[i * LD + i] + cd[i];
+  const bool same_rotated_pair = (pi >> 16) != 0 && (pi & 0xffff) == (pj & 0xffff);
+  return i == j ? diag : (same_rotated_pair ? 0.0 : gen);
+}
+
+// 1/x and 1/sqrt(x) for positive normal x: the hardware estimate refined by
+// two Newton steps (each doubles the number of correct bits).
+__device__ inline double rcp_pos(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return r;
+}
+__device__ inline double rsqrt_pos(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
 }
 
 // Rotation of one pair from the entries of G.
@@ -145,9 +140,11 @@ __device__ inline void make_rotation(double gpp, double gqq, double gpq, double&
                                      double& dt) {
   if (off_diag_large<T>(gpq, gpp, gqq)) {
     const double d = gqq - gpp;
-    double t = 2.0 * gpq / (fabs(d) + sqrt(fma(d, d, 4.0 * gpq * gpq)));
+    const double h2 = fma(d, d, 4.0 * gpq * gpq);   // > 0 since gpq != 0
+    const double h = h2 * rsqrt_pos(h2);
+    double t = 2.0 * gpq * rcp_pos(fabs(d) + h);
     if (d < 0.0) t = -t;
-    c = 1.0 / sqrt(fma(t, t, 1.0));
+    c = rsqrt_pos(fma(t, t, 1.0));
     s = t * c;
     dt = t * gpq;
   } else {
@@ -180,7 +177,8 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   constexpr int MF = (NMAX * NMAX + NT - 1) / NT;            // full entries per thread
   __shared__ double G0s[NMAX * LD], G1s[NMAX * LD];  // two copies of G
   __shared__ double V0s[NMAX * LD], V1s[NMAX * LD];  // two copies of V
-  __shared__ double rc[2][NMAX / 2], rs[2][NMAX / 2], rt[2][NMAX / 2];
+  __shared__ int cu[2][NMAX];
+  __shared__ double ca[2][NMAX], cb[2][NMAX], cd[2][NMAX];
   __shared__ double w[NMAX];
   __shared__ double scal[kScalars];
   __shared__ int s_go;
@@ -384,8 +382,9 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   const int M = N2 - 1;
   const int NP = N2 / 2;
   int sweeps = 0;
-  // One round: read copy SRC, write J^T G J and V J into the other copy, and
-  // (threads tid < NP) the rotations of round r+1.
+  // One round: read copy SRC and the round's column table, write J^T G J and
+  // V J into the other copy; the last wavefront builds the next round's
+  // rotations and column table.
   auto round = [&](auto src_tag, int r) {
     constexpr int SRC = decltype(src_tag)::value;
     const double* Gc = SRC ? G1s : G0s;
@@ -393,10 +392,14 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
     const double* Vc = SRC ? V1s : V0s;
     double* Vn = SRC ? V0s : V1s;
     const int rb = r & 1;
+    const int* tu_ = cu[rb];
+    const double* ta = ca[rb];
+    const double* tb = cb[rb];
+    const double* td = cd[rb];
 #pragma unroll
     for (int q = 0; q < MU; ++q) {
       if (tid + q * NT < nup) {  // slots past n(n+1)/2 are skipped by whole waves
-        const double v = rotated_entry<LD>(ui[q], uj[q], r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
+        const double v = rotated_entry<LD>(ui[q], uj[q], Gc, tu_, ta, tb, td);
         Gn[ui[q] * LD + uj[q]] = v;
         Gn[uj[q] * LD + ui[q]] = v;
       }
@@ -404,27 +407,23 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
 #pragma unroll
     for (int q = 0; q < MF; ++q) {
       if (tid + q * NT < nfull) {
-        const Col cj = column_of(fc[q], r, n, N2, rc[rb], rs[rb]);
-        const int i = fr[q];
-        Vn[i * LD + fc[q]] = fma(cj.a, Vc[i * LD + cj.u], cj.b * Vc[i * LD + cj.v]);
+        const int j = fc[q], i = fr[q];
+        const int pj = tu_[j];
+        Vn[i * LD + j] = fma(ta[j], Vc[i * LD + (pj & 0xff)], tb[j] * Vc[i * LD + ((pj >> 8) & 0xff)]);
       }
     }
-    // The next round's rotations are computed by the last wavefront, which
-    // owns the fewest matrix entries.
     const int kp = tid - (NT - 64);
     if (r + 1 < M && kp >= 0 && kp < NP) {
       int p, q;
       pair_indices(r + 1, kp, N2, p, q);
       double c = 1.0, s = 0.0, dt = 0.0;
       if (q < n) {
-        const double gpp = rotated_entry<LD>(p, p, r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
-        const double gqq = rotated_entry<LD>(q, q, r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
-        const double gpq = rotated_entry<LD>(p, q, r, n, N2, Gc, rc[rb], rs[rb], rt[rb]);
+        const double gpp = rotated_entry<LD>(p, p, Gc, tu_, ta, tb, td);
+        const double gqq = rotated_entry<LD>(q, q, Gc, tu_, ta, tb, td);
+        const double gpq = rotated_entry<LD>(p, q, Gc, tu_, ta, tb, td);
         make_rotation<T>(gpp, gqq, gpq, c, s, dt);
       }
-      rc[rb ^ 1][kp] = c;
-      rs[rb ^ 1][kp] = s;
-      rt[rb ^ 1][kp] = dt;
+      set_pair_columns(p, q, n, c, s, dt, cu[rb ^ 1], ca[rb ^ 1], cb[rb ^ 1], cd[rb ^ 1]);
     }
     __syncthreads();
   };
@@ -444,9 +443,7 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
       pair_indices(0, tid, N2, p, q);
       double c = 1.0, s = 0.0, dt = 0.0;
       if (q < n) make_rotation<T>(G[p * LD + p], G[q * LD + q], G[p * LD + q], c, s, dt);
-      rc[0][tid] = c;
-      rs[0][tid] = s;
-      rt[0][tid] = dt;
+      set_pair_columns(p, q, n, c, s, dt, cu[0], ca[0], cb[0], cd[0]);
     }
     if (!__syncthreads_or(need)) break;
     for (int r = 0; r < M; ++r) {

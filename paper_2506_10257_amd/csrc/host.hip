@@ -50,12 +50,12 @@ struct Geo {
   size_t es = 0;
 };
 
-// Tiles per workgroup.  A function of the solve's own shape only, so a solve
+// Tiles per workgroup: one.  Each workgroup then holds its Gram accumulators
+// only for its own tile (fewer live registers, more resident workgroups), and
+// the hardware overlaps one workgroup's loads with another's arithmetic.  The
+// partial-slot layout depends only on the solve's own shape, so a solve
 // reduces in the same order alone and inside any batch.
-int tiles_per_slot(int tiles) {
-  int tps = tiles / 1024;
-  return std::max(1, std::min(8, tps));
-}
+int tiles_per_slot(int) { return 1; }
 
 bool geometry(int64_t m, int64_t n, int dtype, Geo& g) {
   if (m < 1 || n < 1 || n > RPCA_N_MAX) return false;

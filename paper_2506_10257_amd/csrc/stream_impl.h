@@ -4,7 +4,7 @@
 // frame values in registers (n <= NB, NB a compile-time frame class).  Frame
 // j of row p sits at p + j*m, so for every j a wavefront reads 64 consecutive
 // pixels: each load instruction is one coalesced 256 B (FP32) / 512 B (FP64)
-// segment.  A workgroup walks tiles of kTile rows.
+// segment.  A workgroup processes one tile of kTile rows.
 //
 // k_stream<INIT=true>   : one pass over X.  sum|X|, sum X^2, non-finite count
 //                         (for mu and the stopping test) and the Gram X^T X,
@@ -60,7 +60,7 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   constexpr int NB4 = (NB + 3) / 4 * 4;
   constexpr int LDT = kTile + 1;  // odd row stride: frames of one row fall in different banks
   constexpr size_t kTileBytes = sizeof(T) * NB4 * LDT;
-  constexpr size_t kRedBytes = sizeof(double) * kThreads * 16;
+  constexpr size_t kRedBytes = sizeof(double) * kThreads * 8;  // half a 4x4 block per pass
   constexpr size_t kSmem = kTileBytes > kRedBytes ? kTileBytes : kRedBytes;
   __shared__ __align__(16) unsigned char smem[kSmem];
   __shared__ double wred[kThreads / 64][kScalars];
@@ -106,11 +106,10 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   for (int e = 0; e < 16; ++e) gacc[e] = 0.0;
   double r2 = 0.0, s1 = 0.0, s2 = 0.0, nf = 0.0;
 
-  const int t0 = wi.slot * d.tps;
-  const int t1 = min(t0 + d.tps, d.tiles);
-  for (int t = t0; t < t1; ++t) {
-    // row index within the solve; m < 2^30 so byte offsets fit 32 bits
-    const uint32_t p = static_cast<uint32_t>(t) * kTile + tid;
+  {
+    // one tile per work item; row index within the solve (m < 2^30, so byte
+    // offsets fit 32 bits)
+    const uint32_t p = static_cast<uint32_t>(wi.slot) * kTile + tid;
     const bool valid = p < m;
     if constexpr (INIT) {
 #pragma unroll
@@ -200,17 +199,21 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
 #pragma unroll
     for (int s = 0; s < kScalars; ++s) wred[tid >> 6][s] = sc[s];
   }
-  if (gact) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) red[(gblk * C + gc) * 16 + e] = gacc[e];
-  }
-  __syncthreads();
   double* part = d.partials + static_cast<size_t>(wi.slot) * d.pstride;
-  for (int idx = tid; idx < nblk * 16; idx += kThreads) {
-    const int blk = idx >> 4, e = idx & 15;
-    double s = 0.0;
-    for (int c = 0; c < C; ++c) s += red[(blk * C + c) * 16 + e];
-    part[kScalars + idx] = s;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if (gact) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) red[(gblk * C + gc) * 8 + e] = gacc[half * 8 + e];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nblk * 8; idx += kThreads) {
+      const int blk = idx >> 3, e = idx & 7;
+      double s = 0.0;
+      for (int c = 0; c < C; ++c) s += red[(blk * C + c) * 8 + e];
+      part[kScalars + blk * 16 + half * 8 + e] = s;
+    }
+    __syncthreads();
   }
   if (tid < kScalars) {
     double s = wred[0][tid];
@@ -249,18 +252,16 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
   const gptr<T> So = as_global<T>(d.Sout);
   const bool first = (k == 1);
   const T imu = static_cast<T>(st->imu);
-  const int t0 = wi.slot * d.tps;
-  const int t1 = min(t0 + d.tps, d.tiles);
-  for (int t = t0; t < t1; ++t) {
-    const uint32_t p = static_cast<uint32_t>(t) * kTile + tid;
-    if (p >= m) break;
+  {
+    const uint32_t p = static_cast<uint32_t>(wi.slot) * kTile + tid;
+    if (p >= m) return;
     if (k == 0) {  // sum|X| == 0: L = S = 0
       for (int j = 0; j < n; ++j) {
         const size_t col = static_cast<size_t>(j) * m;
         (L + col)[p] = T(0);
         (So + col)[p] = T(0);
       }
-      continue;
+      return;
     }
     T a[NB];
 #pragma unroll
