@@ -1,0 +1,110 @@
+// Host-side engine of the library (internal).
+//
+//   SolveRec  one problem: its parameters, geometry and the device memory that
+//             holds its iterate buffers, reduction partials, projector,
+//             eigenvectors and state for as long as the solve is active.
+//   Plan      the launch tables (descriptors, work items, group items and
+//             eigensolver id lists) for a set of active solves, split into
+//             lanes: each lane is a stream that runs its own solves' chain
+//             [eigensolve -> streaming update -> group reduction], so one
+//             lane's eigensolves overlap another lane's streaming passes.
+//   Lanes     the streams, events and pinned staging of a run.
+//
+// rpca_solve_many builds one plan for all its problems and runs it to the
+// end; the server builds a plan per quantum from the solves it has admitted.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "rpca.h"
+#include "common.h"
+
+namespace rpca {
+
+struct Geo {
+  int nb = 0, tiles = 0, tps = 1, slots = 0, groups = 0, pstride = 0;
+  size_t es = 0;
+};
+
+// Byte offsets of one solve's device memory.
+struct Big {
+  size_t S0, S1, Y0, Y1, part, gpart, P, V, state, trace, total;
+};
+
+bool geometry(int64_t m, int64_t n, int dtype, Geo& g);
+Big big_layout(int64_t m, int64_t n, const Geo& g);
+
+struct SolveRec {
+  const void* M = nullptr;
+  void* L = nullptr;
+  void* S = nullptr;
+  int64_t m = 0;
+  int32_t n = 0;
+  double lam = -1.0, mu = -1.0, tol = 0.0;
+  int32_t maxit = 1;
+  Geo geo;
+  Big big{};
+  char* mem = nullptr;  // device memory (big.total bytes) or nullptr when not resident
+  int lane = 0;
+  int64_t tag = 0;
+  SolveState st{};      // last state read back
+};
+
+struct LaneRun {
+  std::vector<std::pair<int, std::pair<int, int>>> classes;  // (nb, (item offset, count))
+  std::vector<std::pair<int, std::pair<int, int>>> eigs;     // (class, (id offset, count))
+  int gitem_off = 0, gitem_cnt = 0;
+  std::vector<int> solves;                                   // plan-local solve indices
+};
+
+struct Plan {
+  int dtype = RPCA_F32;
+  int count = 0;
+  std::vector<SolveRec*> recs;
+  std::vector<LaneRun> lanes;
+  std::vector<unsigned char> host;  // staging copy of the control block
+  char* ctrl = nullptr;             // device control block
+  SolveDesc* descs = nullptr;
+  WorkItem* items = nullptr;
+  GroupItem* gitems = nullptr;
+  int32_t* ids = nullptr;
+  SolveState* gathered = nullptr;   // k_gather_states output (count states)
+};
+
+// Build the control block for `recs` (each rec's lane in [0, nlanes)) and
+// upload it on `stream`.  Returns a status code.
+int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int dtype,
+               hipStream_t stream);
+void plan_free(Plan& plan, hipStream_t stream);
+
+struct Lanes {
+  std::vector<hipStream_t> s;
+  std::vector<hipEvent_t> join;   // per lane
+  hipEvent_t fork = nullptr;
+  SolveState* pinned[2] = {nullptr, nullptr};
+  hipEvent_t snap[2] = {nullptr, nullptr};
+  int pinned_count = 0;
+};
+
+int lanes_create(Lanes& L, int nlanes);
+void lanes_destroy(Lanes& L);
+int lanes_reserve_pinned(Lanes& L, int count);
+
+// Enqueue on the lanes.  Each returns hipSuccess or the failing call's error.
+hipError_t enqueue_reset_states(const Plan& plan, hipStream_t s);
+hipError_t enqueue_init(const Plan& plan, const Lanes& L);
+hipError_t enqueue_iterations(const Plan& plan, const Lanes& L, int iters);
+hipError_t enqueue_finalize(const Plan& plan, const Lanes& L);
+// Join every lane into lane 0, gather the plan's solve states into pinned
+// buffer `slot` and record snap[slot].
+hipError_t enqueue_snapshot(const Plan& plan, Lanes& L, int slot);
+
+void set_error(const char* what, hipError_t e);
+void set_error_text(const char* text);
+
+int nb_class(int64_t n, int dtype);
+
+}  // namespace rpca

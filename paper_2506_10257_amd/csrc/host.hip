@@ -1,23 +1,29 @@
-// Host runtime of librpca_mi355x: the C ABI declared in include/rpca.h.
+// Host runtime of librpca_mi355x: the engine (plans, lanes, enqueue
+// helpers) and the solve entry points of the C ABI (include/rpca.h).
 //
-// A call (one solve or a batch) is laid out as follows:
-//   * one stream-ordered device allocation holds the control block (solve
-//     descriptors, the work-item and group tables, solve states) and
-//     every solve's iterate buffers, reduction partials, Gram, projector and
-//     eigenvectors;
-//   * the init pass runs once per frame class, then iterations are enqueued
-//     in chunks of [eigensolve per eigensolver class, update pass per frame
-//     class, group reduction];
-//     a solve that has finished makes its later launches exit at once, so the
-//     host only reads the solve states back between chunks;
-//   * the finalize pass writes L and S, the states are read back, and the
-//     allocation is returned to the pool.
+// A call of rpca_solve_many:
+//   * validates every problem and gives each its own device memory (one
+//     stream-ordered allocation for the call);
+//   * assigns the problems to lanes (streams) balancing their matrix sizes,
+//     and builds one plan: solve descriptors, the streaming work items per
+//     frame class, the group-reduction items and the eigensolver id lists;
+//   * runs the init pass, then chunks of iterations.  A chunk is captured
+//     once as a graph (all lanes, forked from and joined into lane 0) and
+//     replayed; after each replay one small kernel gathers the solve states
+//     and they are copied to pinned host memory.  The next chunk is enqueued
+//     before the previous snapshot is inspected, so the host round trip
+//     overlaps device work; a solve that has finished makes its later
+//     launches exit at once;
+//   * runs the finalize pass, reads the states back and frees the memory.
+// With kernel timing enabled the chunk is launched directly (no graph) with
+// HIP events around every launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <utility>
@@ -25,85 +31,31 @@
 
 #include "rpca.h"
 #include "common.h"
+#include "engine.h"
 #include "launch.h"
 
-using namespace rpca;
+namespace rpca {
 
 namespace {
 
-constexpr int kChunkFirst = 8;
-constexpr int kChunkMax = 64;
-
-int nb_class(int64_t n, int dtype) {
-  if (dtype == RPCA_F32) {
-    for (int c : kClassesF32)
-      if (n <= c) return c;
-  } else {
-    for (int c : kClassesF64)
-      if (n <= c) return c;
-  }
-  return 0;
-}
-
-struct Geo {
-  int nb = 0, tiles = 0, tps = 1, slots = 0, groups = 0, pstride = 0;
-  size_t es = 0;
-};
-
-// Tiles per workgroup: one.  Each workgroup then holds its Gram accumulators
-// only for its own tile (fewer live registers, more resident workgroups), and
-// the hardware overlaps one workgroup's loads with another's arithmetic.  The
-// partial-slot layout depends only on the solve's own shape, so a solve
-// reduces in the same order alone and inside any batch.
-int tiles_per_slot(int) { return 1; }
-
-bool geometry(int64_t m, int64_t n, int dtype, Geo& g) {
-  if (m < 1 || n < 1 || n > RPCA_N_MAX) return false;
-  g.nb = nb_class(n, dtype);
-  if (g.nb == 0 || n > kEigMaxN) return false;
-  if (m >= (int64_t(1) << 30)) return false;  // row offsets are 32-bit byte offsets
-  const int64_t tiles = (m + kTile - 1) / kTile;
-  g.tiles = static_cast<int>(tiles);
-  g.tps = tiles_per_slot(g.tiles);
-  g.slots = (g.tiles + g.tps - 1) / g.tps;
-  g.groups = (g.slots + kGroup - 1) / kGroup;
-  g.pstride = pstride_for(g.nb);
-  g.es = dtype == RPCA_F32 ? 4 : 8;
-  return true;
-}
+constexpr int kGraphChunk = 16;
+constexpr int kDirectChunkFirst = 8;
+constexpr int kDirectChunkMax = 64;
+constexpr int kMaxLanes = 3;
 
 size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-struct Big {
-  size_t S0, S1, Y0, Y1, part, gpart, P, V, trace, total;
-};
-
-Big big_layout(int64_t m, int64_t n, const Geo& g) {
-  Big b{};
-  size_t o = 0;
-  const size_t mat = al256(static_cast<size_t>(m) * static_cast<size_t>(n) * g.es);
-  b.S0 = o; o += mat;
-  b.S1 = o; o += mat;
-  b.Y0 = o; o += mat;
-  b.Y1 = o; o += mat;
-  b.part = o; o += al256(static_cast<size_t>(g.slots) * g.pstride * sizeof(double));
-  b.gpart = o; o += al256(static_cast<size_t>(g.groups) * g.pstride * sizeof(double));
-  b.P = o; o += al256(static_cast<size_t>(g.nb) * g.nb * g.es);
-  b.V = o; o += al256(static_cast<size_t>(g.nb) * g.nb * sizeof(double));
-  b.trace = o;
-#ifdef RPCA_TRACE
-  o += al256(static_cast<size_t>(g.slots) * 4 * sizeof(int64_t));
-#endif
-  b.total = o;
-  return b;
-}
-
-bool overlap(const void* a, const void* b, size_t bytes) {
-  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-  return x < y + bytes && y < x + bytes;
-}
+thread_local char g_last_error[512] = "";
 
 // ---------------------------------------------------------------- profiling
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  int kind = 0;   // 0 init, 1 eig, 2 update, 3 finalize
+  int iter = 0;   // eig/update: 1-based iteration of the launch
+  int lane = 0;
+  int cls = -1;   // update: index into the lane's classes
+};
+
 struct Profile {
   std::mutex mu;
   bool on = false;
@@ -113,12 +65,28 @@ struct Profile {
 };
 Profile g_prof;
 
-struct EvPair {
-  hipEvent_t a = nullptr, b = nullptr;
-  int kind = 0;        // 0 init, 1 eig, 2 update, 3 finalize
-  int iter = 0;        // eig/update: 1-based launch index
-  int cls = -1;        // update: class index
-};
+bool profiling_on() {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  return g_prof.on;
+}
+
+thread_local std::vector<EvPair>* t_evs = nullptr;  // set while a profiled run enqueues
+
+void ev_begin(hipStream_t s, int kind, int iter, int lane, int cls) {
+  if (!t_evs) return;
+  EvPair e;
+  e.kind = kind;
+  e.iter = iter;
+  e.lane = lane;
+  e.cls = cls;
+  (void)hipEventCreate(&e.a);
+  (void)hipEventCreate(&e.b);
+  (void)hipEventRecord(e.a, s);
+  t_evs->push_back(e);
+}
+void ev_end(hipStream_t s) {
+  if (t_evs) (void)hipEventRecord(t_evs->back().b, s);
+}
 
 // ------------------------------------------------------------- device pool
 std::once_flag g_pool_once[64];
@@ -133,21 +101,27 @@ void setup_pool(int dev) {
   });
 }
 
-struct ClassRun {
-  int nb;
-  int item_off, item_cnt;
-  std::vector<int> solves;
-};
+bool overlap(const void* a, const void* b, size_t bytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+hipError_t launch_stream(int dtype, int nb, int mode, int grid, hipStream_t s, const SolveDesc* d,
+                         const WorkItem* it) {
+  return dtype == RPCA_F32 ? launch_stream_f32(nb, mode, grid, s, d, it)
+                           : launch_stream_f64(nb, mode, grid, s, d, it);
+}
 
 #ifdef RPCA_TRACE
 // Trace builds: per-phase eigensolve times and the workgroup timeline of the
 // last update pass of the first solve, printed to stderr (10 ns ticks).
-void trace_report(const SolveState& st, const void* dtrace, int slots, hipStream_t stream) {
-  std::vector<int64_t> t(static_cast<size_t>(slots) * 4);
-  if (hipMemcpyAsync(t.data(), dtrace, t.size() * sizeof(int64_t), hipMemcpyDeviceToHost, stream) !=
-          hipSuccess ||
+void trace_report(const SolveRec& r, hipStream_t stream) {
+  std::vector<int64_t> t(static_cast<size_t>(r.geo.slots) * 4);
+  if (hipMemcpyAsync(t.data(), r.mem + r.big.trace, t.size() * sizeof(int64_t),
+                     hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return;
+  const SolveState& st = r.st;
   const double it = st.iter > 0 ? st.iter : 1;
   std::fprintf(stderr,
                "[trace] eig us/iter: reduce+control %.2f warm %.2f jacobi %.2f project %.2f "
@@ -156,7 +130,7 @@ void trace_report(const SolveState& st, const void* dtrace, int slots, hipStream
                st.trace[3] * 0.01 / it, st.sweeps_total / it);
   int64_t b0 = INT64_MAX, b1 = 0, e1 = 0, e2 = 0;
   double sum_tiles = 0;
-  for (int s = 0; s < slots; ++s) {
+  for (int s = 0; s < r.geo.slots; ++s) {
     b0 = std::min(b0, t[s * 4 + 0]);
     b1 = std::max(b1, t[s * 4 + 0]);
     e1 = std::max(e1, t[s * 4 + 1]);
@@ -166,36 +140,358 @@ void trace_report(const SolveState& st, const void* dtrace, int slots, hipStream
   std::fprintf(stderr,
                "[trace] update us: last WG start %.2f, tiles done %.2f, partials %.2f; "
                "mean WG tile time %.2f\n",
-               (b1 - b0) * 0.01, (e1 - b0) * 0.01, (e2 - b0) * 0.01, sum_tiles / slots * 0.01);
+               (b1 - b0) * 0.01, (e1 - b0) * 0.01, (e2 - b0) * 0.01, sum_tiles / r.geo.slots * 0.01);
 }
 #endif
 
-thread_local char g_last_error[512] = "";
+}  // namespace
 
+// ------------------------------------------------------------------ errors
 void set_error(const char* what, hipError_t e) {
   std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e),
                 static_cast<int>(e));
 }
+void set_error_text(const char* text) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", text); }
 
-#define CK(expr)                          \
-  do {                                    \
-    hipError_t e_ = (expr);               \
-    if (e_ != hipSuccess) {               \
-      set_error(#expr, e_);               \
-      rc = RPCA_ERR_DEVICE;               \
-      goto done;                          \
-    }                                     \
+// ---------------------------------------------------------------- geometry
+int nb_class(int64_t n, int dtype) {
+  if (dtype == RPCA_F32) {
+    for (int c : kClassesF32)
+      if (n <= c) return c;
+  } else {
+    for (int c : kClassesF64)
+      if (n <= c) return c;
+  }
+  return 0;
+}
+
+bool geometry(int64_t m, int64_t n, int dtype, Geo& g) {
+  if (m < 1 || n < 1 || n > RPCA_N_MAX) return false;
+  g.nb = nb_class(n, dtype);
+  if (g.nb == 0 || n > kEigMaxN) return false;
+  if (m >= (int64_t(1) << 30)) return false;  // row offsets are 32-bit byte offsets
+  const int64_t tiles = (m + kTile - 1) / kTile;
+  g.tiles = static_cast<int>(tiles);
+  g.tps = 1;  // one tile per work item (and per partial slot)
+  g.slots = g.tiles;
+  g.groups = (g.slots + kGroup - 1) / kGroup;
+  g.pstride = pstride_for(g.nb);
+  g.es = dtype == RPCA_F32 ? 4 : 8;
+  return true;
+}
+
+Big big_layout(int64_t m, int64_t n, const Geo& g) {
+  Big b{};
+  size_t o = 0;
+  const size_t mat = al256(static_cast<size_t>(m) * static_cast<size_t>(n) * g.es);
+  b.S0 = o; o += mat;
+  b.S1 = o; o += mat;
+  b.Y0 = o; o += mat;
+  b.Y1 = o; o += mat;
+  b.part = o; o += al256(static_cast<size_t>(g.slots) * g.pstride * sizeof(double));
+  b.gpart = o; o += al256(static_cast<size_t>(g.groups) * g.pstride * sizeof(double));
+  b.P = o; o += al256(static_cast<size_t>(g.nb) * g.nb * g.es);
+  b.V = o; o += al256(static_cast<size_t>(g.nb) * g.nb * sizeof(double));
+  b.state = o; o += al256(sizeof(SolveState));
+  b.trace = o;
+#ifdef RPCA_TRACE
+  o += al256(static_cast<size_t>(g.slots) * 4 * sizeof(int64_t));
+#endif
+  b.total = o;
+  return b;
+}
+
+// --------------------------------------------------------------------- plan
+int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int dtype,
+               hipStream_t stream) {
+  plan.dtype = dtype;
+  plan.count = static_cast<int>(recs.size());
+  plan.recs = recs;
+  plan.lanes.assign(nlanes, LaneRun{});
+  for (int i = 0; i < plan.count; ++i) plan.lanes[recs[i]->lane].solves.push_back(i);
+
+  std::vector<WorkItem> items;
+  std::vector<GroupItem> gitems;
+  std::vector<int32_t> ids;
+  for (LaneRun& lr : plan.lanes) {
+    std::vector<int> nbs;
+    for (int i : lr.solves)
+      if (std::find(nbs.begin(), nbs.end(), recs[i]->geo.nb) == nbs.end()) nbs.push_back(recs[i]->geo.nb);
+    for (int nb : nbs) {
+      const int off = static_cast<int>(items.size());
+      for (int i : lr.solves)
+        if (recs[i]->geo.nb == nb)
+          for (int q = 0; q < recs[i]->geo.slots; ++q) items.push_back(WorkItem{i, q});
+      lr.classes.push_back({nb, {off, static_cast<int>(items.size()) - off}});
+    }
+    for (int cls : {16, 32, 64}) {
+      const int off = static_cast<int>(ids.size());
+      for (int i : lr.solves)
+        if (eig_class(recs[i]->n) == cls) ids.push_back(i);
+      const int cnt = static_cast<int>(ids.size()) - off;
+      if (cnt > 0) lr.eigs.push_back({cls, {off, cnt}});
+    }
+    lr.gitem_off = static_cast<int>(gitems.size());
+    for (int i : lr.solves)
+      for (int g = 0; g < recs[i]->geo.groups; ++g) gitems.push_back(GroupItem{i, g});
+    lr.gitem_cnt = static_cast<int>(gitems.size()) - lr.gitem_off;
+  }
+
+  const size_t off_desc = 0;
+  const size_t off_items = al256(off_desc + sizeof(SolveDesc) * plan.count);
+  const size_t off_gitems = al256(off_items + sizeof(WorkItem) * items.size());
+  const size_t off_ids = al256(off_gitems + sizeof(GroupItem) * gitems.size());
+  const size_t off_gath = al256(off_ids + sizeof(int32_t) * ids.size());
+  const size_t bytes = al256(off_gath + sizeof(SolveState) * plan.count);
+  plan.host.assign(bytes, 0);
+
+  SolveDesc* dh = reinterpret_cast<SolveDesc*>(plan.host.data() + off_desc);
+  for (int i = 0; i < plan.count; ++i) {
+    const SolveRec& r = *recs[i];
+    char* b = r.mem;
+    SolveDesc& d = dh[i];
+    std::memset(&d, 0, sizeof(d));
+    d.X = r.M;
+    d.S[0] = b + r.big.S0;
+    d.S[1] = b + r.big.S1;
+    d.Y[0] = b + r.big.Y0;
+    d.Y[1] = b + r.big.Y1;
+    d.Lout = r.L;
+    d.Sout = r.S;
+    d.partials = reinterpret_cast<double*>(b + r.big.part);
+    d.gpartials = reinterpret_cast<double*>(b + r.big.gpart);
+    d.P = b + r.big.P;
+    d.V = reinterpret_cast<double*>(b + r.big.V);
+    d.st = reinterpret_cast<SolveState*>(b + r.big.state);
+#ifdef RPCA_TRACE
+    d.wgtrace = reinterpret_cast<int64_t*>(b + r.big.trace);
+#endif
+    d.m = r.m;
+    d.n = r.n;
+    d.nb = r.geo.nb;
+    d.tiles = r.geo.tiles;
+    d.tps = r.geo.tps;
+    d.slots = r.geo.slots;
+    d.groups = r.geo.groups;
+    d.pstride = r.geo.pstride;
+    d.maxit = r.maxit;
+    d.lam_in = r.lam;
+    d.mu_in = r.mu;
+    d.tol = r.tol;
+  }
+  if (!items.empty())
+    std::memcpy(plan.host.data() + off_items, items.data(), sizeof(WorkItem) * items.size());
+  if (!gitems.empty())
+    std::memcpy(plan.host.data() + off_gitems, gitems.data(), sizeof(GroupItem) * gitems.size());
+  if (!ids.empty()) std::memcpy(plan.host.data() + off_ids, ids.data(), sizeof(int32_t) * ids.size());
+
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&plan.ctrl), bytes, stream);
+  if (e != hipSuccess || plan.ctrl == nullptr) {
+    set_error("hipMallocAsync(control block)", e);
+    (void)hipGetLastError();
+    plan.ctrl = nullptr;
+    return RPCA_ERR_NOMEM;
+  }
+  e = hipMemcpyAsync(plan.ctrl, plan.host.data(), bytes, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) {
+    set_error("hipMemcpyAsync(control block)", e);
+    return RPCA_ERR_DEVICE;
+  }
+  plan.descs = reinterpret_cast<SolveDesc*>(plan.ctrl + off_desc);
+  plan.items = reinterpret_cast<WorkItem*>(plan.ctrl + off_items);
+  plan.gitems = reinterpret_cast<GroupItem*>(plan.ctrl + off_gitems);
+  plan.ids = reinterpret_cast<int32_t*>(plan.ctrl + off_ids);
+  plan.gathered = reinterpret_cast<SolveState*>(plan.ctrl + off_gath);
+  return RPCA_OK;
+}
+
+void plan_free(Plan& plan, hipStream_t stream) {
+  if (plan.ctrl) (void)hipFreeAsync(plan.ctrl, stream);
+  plan.ctrl = nullptr;
+}
+
+// -------------------------------------------------------------------- lanes
+int lanes_create(Lanes& L, int nlanes) {
+  L.s.assign(nlanes, nullptr);
+  L.join.assign(nlanes, nullptr);
+  for (int i = 0; i < nlanes; ++i) {
+    hipError_t e = hipStreamCreateWithFlags(&L.s[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&L.join[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      set_error("hipStreamCreateWithFlags/hipEventCreate(lane)", e);
+      return RPCA_ERR_DEVICE;
+    }
+  }
+  hipError_t e = hipEventCreateWithFlags(&L.fork, hipEventDisableTiming);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&L.snap[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    set_error("hipEventCreate(lanes)", e);
+    return RPCA_ERR_DEVICE;
+  }
+  return RPCA_OK;
+}
+
+int lanes_reserve_pinned(Lanes& L, int count) {
+  if (count <= L.pinned_count) return RPCA_OK;
+  for (int k = 0; k < 2; ++k) {
+    if (L.pinned[k]) (void)hipHostFree(L.pinned[k]);
+    L.pinned[k] = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&L.pinned[k]), sizeof(SolveState) * count) != hipSuccess) {
+      set_error_text("hipHostMalloc(state snapshots) failed");
+      L.pinned_count = 0;
+      return RPCA_ERR_NOMEM;
+    }
+  }
+  L.pinned_count = count;
+  return RPCA_OK;
+}
+
+void lanes_destroy(Lanes& L) {
+  for (auto s : L.s)
+    if (s) (void)hipStreamSynchronize(s);
+  for (auto e : L.join)
+    if (e) (void)hipEventDestroy(e);
+  for (auto s : L.s)
+    if (s) (void)hipStreamDestroy(s);
+  if (L.fork) (void)hipEventDestroy(L.fork);
+  for (int k = 0; k < 2; ++k) {
+    if (L.snap[k]) (void)hipEventDestroy(L.snap[k]);
+    if (L.pinned[k]) (void)hipHostFree(L.pinned[k]);
+    L.snap[k] = nullptr;
+    L.pinned[k] = nullptr;
+  }
+  L.s.clear();
+  L.join.clear();
+  L.fork = nullptr;
+  L.pinned_count = 0;
+}
+
+// ------------------------------------------------------------------ enqueue
+#define EQ(expr)                   \
+  do {                             \
+    const hipError_t e_ = (expr);  \
+    if (e_ != hipSuccess) {        \
+      set_error(#expr, e_);        \
+      return e_;                   \
+    }                              \
   } while (0)
 
-int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStream_t stream) {
+hipError_t enqueue_reset_states(const Plan& plan, hipStream_t s) {
+  EQ(launch_reset_states(plan.count, s, plan.descs));
+  return hipSuccess;
+}
+
+// Lanes >= 1 wait for lane 0's work so far (the control block upload).
+static hipError_t fork_lanes(const Lanes& L) {
+  if (L.s.size() <= 1) return hipSuccess;
+  EQ(hipEventRecord(L.fork, L.s[0]));
+  for (size_t i = 1; i < L.s.size(); ++i) EQ(hipStreamWaitEvent(L.s[i], L.fork, 0));
+  return hipSuccess;
+}
+
+hipError_t enqueue_init(const Plan& plan, const Lanes& L) {
+  EQ(fork_lanes(L));
+  for (size_t l = 0; l < plan.lanes.size(); ++l) {
+    const LaneRun& lr = plan.lanes[l];
+    hipStream_t s = L.s[l];
+    for (size_t c = 0; c < lr.classes.size(); ++c) {
+      ev_begin(s, 0, 0, static_cast<int>(l), static_cast<int>(c));
+      EQ(launch_stream(plan.dtype, lr.classes[c].first, kModeInit, lr.classes[c].second.second, s,
+                       plan.descs, plan.items + lr.classes[c].second.first));
+      ev_end(s);
+    }
+    EQ(launch_reduce(lr.gitem_cnt, s, plan.descs, plan.gitems + lr.gitem_off));
+  }
+  return hipSuccess;
+}
+
+// `first_iter` numbers the launches for kernel timing (1-based).
+static hipError_t enqueue_iterations_at(const Plan& plan, const Lanes& L, int iters, int first_iter) {
+  for (size_t l = 0; l < plan.lanes.size(); ++l) {
+    const LaneRun& lr = plan.lanes[l];
+    hipStream_t s = L.s[l];
+    for (int k = 0; k < iters; ++k) {
+      for (const auto& er : lr.eigs) {
+        ev_begin(s, 1, first_iter + k, static_cast<int>(l), -1);
+        EQ(launch_eig(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s, plan.descs,
+                      plan.ids + er.second.first));
+        ev_end(s);
+      }
+      for (size_t c = 0; c < lr.classes.size(); ++c) {
+        ev_begin(s, 2, first_iter + k, static_cast<int>(l), static_cast<int>(c));
+        EQ(launch_stream(plan.dtype, lr.classes[c].first, kModeUpdate, lr.classes[c].second.second,
+                         s, plan.descs, plan.items + lr.classes[c].second.first));
+        ev_end(s);
+      }
+      EQ(launch_reduce(lr.gitem_cnt, s, plan.descs, plan.gitems + lr.gitem_off));
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue_iterations(const Plan& plan, const Lanes& L, int iters) {
+  return enqueue_iterations_at(plan, L, iters, 1);
+}
+
+hipError_t enqueue_finalize(const Plan& plan, const Lanes& L) {
+  for (size_t l = 0; l < plan.lanes.size(); ++l) {
+    const LaneRun& lr = plan.lanes[l];
+    hipStream_t s = L.s[l];
+    for (size_t c = 0; c < lr.classes.size(); ++c) {
+      ev_begin(s, 3, 0, static_cast<int>(l), static_cast<int>(c));
+      EQ(launch_stream(plan.dtype, lr.classes[c].first, kModeFinalize, lr.classes[c].second.second,
+                       s, plan.descs, plan.items + lr.classes[c].second.first));
+      ev_end(s);
+    }
+  }
+  return hipSuccess;
+}
+
+static hipError_t join_lanes(const Lanes& L) {
+  for (size_t i = 1; i < L.s.size(); ++i) {
+    EQ(hipEventRecord(L.join[i], L.s[i]));
+    EQ(hipStreamWaitEvent(L.s[0], L.join[i], 0));
+  }
+  return hipSuccess;
+}
+
+hipError_t enqueue_snapshot(const Plan& plan, Lanes& L, int slot) {
+  EQ(join_lanes(L));
+  EQ(launch_gather_states(plan.count, L.s[0], plan.descs, plan.gathered));
+  EQ(hipMemcpyAsync(L.pinned[slot], plan.gathered, sizeof(SolveState) * plan.count,
+                    hipMemcpyDeviceToHost, L.s[0]));
+  EQ(hipEventRecord(L.snap[slot], L.s[0]));
+  return hipSuccess;
+}
+
+#undef EQ
+
+// ---------------------------------------------------------------- run_batch
+namespace {
+
+#define CK(expr)                                  \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) {                       \
+      if (!g_last_error[0]) set_error(#expr, e_); \
+      rc = RPCA_ERR_DEVICE;                       \
+      goto done;                                  \
+    }                                             \
+  } while (0)
+
+bool graphs_disabled() {
+  const char* v = std::getenv("RPCA_NO_GRAPH");
+  return v && v[0] && v[0] != '0';
+}
+
+int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStream_t user) {
   g_last_error[0] = '\0';
   if (count < 1 || probs == nullptr) return RPCA_ERR_ARG;
   if (dtype != RPCA_F32 && dtype != RPCA_F64) return RPCA_ERR_ARG;
   if (gram_mode != RPCA_GRAM_DEFAULT && gram_mode != RPCA_GRAM_BF16X3) return RPCA_ERR_ARG;
   if (gram_mode == RPCA_GRAM_BF16X3) return RPCA_ERR_UNSUPPORTED;
 
-  std::vector<Geo> geo(count);
-  std::vector<Big> big(count);
+  std::vector<SolveRec> recs(count);
   for (int i = 0; i < count; ++i) {
     rpca_problem& p = probs[i];
     if (!p.M || !p.L || !p.S || p.m < 1 || p.n < 1 || p.n > RPCA_N_MAX || p.maxit < 1)
@@ -204,57 +500,34 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
     const size_t bytes = static_cast<size_t>(p.m) * static_cast<size_t>(p.n) * (dtype == RPCA_F32 ? 4 : 8);
     if (overlap(p.M, p.L, bytes) || overlap(p.M, p.S, bytes) || overlap(p.L, p.S, bytes))
       return RPCA_ERR_ARG;
-    if (!geometry(p.m, p.n, dtype, geo[i])) return RPCA_ERR_UNSUPPORTED;
-    big[i] = big_layout(p.m, p.n, geo[i]);
+    SolveRec& r = recs[i];
+    if (!geometry(p.m, p.n, dtype, r.geo)) return RPCA_ERR_UNSUPPORTED;
+    r.big = big_layout(p.m, p.n, r.geo);
+    r.M = p.M;
+    r.L = p.L;
+    r.S = p.S;
+    r.m = p.m;
+    r.n = static_cast<int32_t>(p.n);
+    r.lam = p.lambda;
+    r.mu = p.mu;
+    r.tol = p.tol;
+    r.maxit = p.maxit;
   }
 
-  // Frame classes and the work-item table.
-  std::vector<ClassRun> classes;
-  for (int i = 0; i < count; ++i) {
-    auto it = std::find_if(classes.begin(), classes.end(),
-                           [&](const ClassRun& c) { return c.nb == geo[i].nb; });
-    if (it == classes.end()) {
-      classes.push_back(ClassRun{geo[i].nb, 0, 0, {}});
-      it = classes.end() - 1;
+  // Lanes: balance the matrix sizes, largest first.
+  const int nlanes = std::min(count, kMaxLanes);
+  {
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+      return recs[a].m * recs[a].n > recs[b].m * recs[b].n;
+    });
+    std::vector<double> load(nlanes, 0.0);
+    for (int i : order) {
+      const int l = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+      recs[i].lane = l;
+      load[l] += static_cast<double>(recs[i].m) * recs[i].n;
     }
-    it->solves.push_back(i);
-  }
-  std::vector<WorkItem> items;
-  for (auto& c : classes) {
-    c.item_off = static_cast<int>(items.size());
-    for (int s : c.solves)
-      for (int q = 0; q < geo[s].slots; ++q) items.push_back(WorkItem{s, q});
-    c.item_cnt = static_cast<int>(items.size()) - c.item_off;
-  }
-
-  // Eigensolver classes and their solve-id lists.
-  std::vector<int32_t> eig_ids;
-  std::vector<std::pair<int, std::pair<int, int>>> eig_runs;  // (class, (offset, count))
-  for (int cls : {16, 32, 64}) {
-    const int off = static_cast<int>(eig_ids.size());
-    for (int i = 0; i < count; ++i)
-      if (eig_class(static_cast<int>(probs[i].n)) == cls) eig_ids.push_back(i);
-    const int cnt = static_cast<int>(eig_ids.size()) - off;
-    if (cnt > 0) eig_runs.push_back({cls, {off, cnt}});
-  }
-
-  // Group items of the reduction launch.
-  std::vector<GroupItem> gitems;
-  for (int i = 0; i < count; ++i)
-    for (int g = 0; g < geo[i].groups; ++g) gitems.push_back(GroupItem{i, g});
-
-  // Control block: descs | items | group items | eig ids | states.
-  const size_t off_desc = 0;
-  const size_t off_items = al256(off_desc + sizeof(SolveDesc) * count);
-  const size_t off_gitems = al256(off_items + sizeof(WorkItem) * items.size());
-  const size_t off_ids = al256(off_gitems + sizeof(GroupItem) * gitems.size());
-  const size_t off_state = al256(off_ids + sizeof(int32_t) * eig_ids.size());
-  const size_t ctrl_bytes = al256(off_state + sizeof(SolveState) * count);
-  size_t total = ctrl_bytes;
-  std::vector<size_t> base(count);
-  for (int i = 0; i < count; ++i) {
-    base[i] = total;
-    total += big[i].total;
   }
 
   int dev = 0;
@@ -268,216 +541,217 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   }
   setup_pool(dev);
 
+  const bool prof = profiling_on();
+  const bool use_graph = !prof && !graphs_disabled();
   int rc = RPCA_OK;
   char* arena = nullptr;
-  std::vector<unsigned char> ctrl_h(ctrl_bytes, 0);
-  SolveState* st_h = nullptr;
+  Lanes L;
+  Plan plan;
   std::vector<EvPair> evs;
-  bool prof = false;
-  {
-    std::lock_guard<std::mutex> lk(g_prof.mu);
-    prof = g_prof.on;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<SolveRec*> ptrs(count);
+  int maxit_all = 0;
+  for (int i = 0; i < count; ++i) {
+    ptrs[i] = &recs[i];
+    maxit_all = std::max(maxit_all, recs[i].maxit);
   }
 
+  rc = lanes_create(L, nlanes);
+  if (rc != RPCA_OK) {
+    lanes_destroy(L);
+    return rc;
+  }
+  rc = lanes_reserve_pinned(L, count);
+  if (rc != RPCA_OK) {
+    lanes_destroy(L);
+    return rc;
+  }
+  hipStream_t s0 = L.s[0];
+  if (prof) t_evs = &evs;
+
   {
-    hipError_t ae = hipMallocAsync(reinterpret_cast<void**>(&arena), total, stream);
-    if (ae != hipSuccess || arena == nullptr) {
-      set_error("hipMallocAsync(workspace)", ae);
-      (void)hipGetLastError();
-      return RPCA_ERR_NOMEM;
+    // inputs are produced on the caller's stream
+    hipError_t e = hipStreamSynchronize(user);
+    if (e != hipSuccess) {
+      set_error("hipStreamSynchronize(caller stream)", e);
+      rc = RPCA_ERR_DEVICE;
+      goto done;
     }
-  }
-  if (hipHostMalloc(reinterpret_cast<void**>(&st_h), sizeof(SolveState) * count) != hipSuccess) {
-    (void)hipFreeAsync(arena, stream);
-    return RPCA_ERR_NOMEM;
-  }
-
-  {
-    SolveDesc* dh = reinterpret_cast<SolveDesc*>(ctrl_h.data() + off_desc);
-    SolveState* sd = reinterpret_cast<SolveState*>(arena + off_state);
+    size_t total = 0;
+    std::vector<size_t> base(count);
     for (int i = 0; i < count; ++i) {
-      const rpca_problem& p = probs[i];
-      char* b = arena + base[i];
-      SolveDesc& d = dh[i];
-      std::memset(&d, 0, sizeof(d));
-      d.X = p.M;
-      d.S[0] = b + big[i].S0;
-      d.S[1] = b + big[i].S1;
-      d.Y[0] = b + big[i].Y0;
-      d.Y[1] = b + big[i].Y1;
-      d.Lout = p.L;
-      d.Sout = p.S;
-      d.partials = reinterpret_cast<double*>(b + big[i].part);
-      d.gpartials = reinterpret_cast<double*>(b + big[i].gpart);
-      d.P = b + big[i].P;
-      d.V = reinterpret_cast<double*>(b + big[i].V);
-      d.st = sd + i;
-#ifdef RPCA_TRACE
-      d.wgtrace = reinterpret_cast<int64_t*>(b + big[i].trace);
-#endif
-      d.m = p.m;
-      d.n = static_cast<int32_t>(p.n);
-      d.nb = geo[i].nb;
-      d.tiles = geo[i].tiles;
-      d.tps = geo[i].tps;
-      d.slots = geo[i].slots;
-      d.groups = geo[i].groups;
-      d.pstride = geo[i].pstride;
-      d.maxit = p.maxit;
-      d.lam_in = p.lambda;
-      d.mu_in = p.mu;
-      d.tol = p.tol;
+      base[i] = total;
+      total += recs[i].big.total;
     }
-    std::memcpy(ctrl_h.data() + off_items, items.data(), sizeof(WorkItem) * items.size());
-    std::memcpy(ctrl_h.data() + off_gitems, gitems.data(), sizeof(GroupItem) * gitems.size());
-    std::memcpy(ctrl_h.data() + off_ids, eig_ids.data(), sizeof(int32_t) * eig_ids.size());
-    // states start at zero (ctrl_h is zero-filled)
+    e = hipMallocAsync(reinterpret_cast<void**>(&arena), total, s0);
+    if (e != hipSuccess || arena == nullptr) {
+      set_error("hipMallocAsync(workspace)", e);
+      (void)hipGetLastError();
+      arena = nullptr;
+      rc = RPCA_ERR_NOMEM;
+      goto done;
+    }
+    for (int i = 0; i < count; ++i) recs[i].mem = arena + base[i];
   }
+  rc = plan_build(plan, ptrs, nlanes, dtype, s0);
+  if (rc != RPCA_OK) goto done;
+  CK(enqueue_reset_states(plan, s0));
+  CK(enqueue_init(plan, L));
 
   {
-    const SolveDesc* descs = reinterpret_cast<const SolveDesc*>(arena + off_desc);
-    const WorkItem* items_d = reinterpret_cast<const WorkItem*>(arena + off_items);
-    const int32_t* ids_d = reinterpret_cast<const int32_t*>(arena + off_ids);
-    const GroupItem* gitems_d = reinterpret_cast<const GroupItem*>(arena + off_gitems);
-    const int ngroups = static_cast<int>(gitems.size());
-    auto launch_class = [&](const ClassRun& c, int mode) -> hipError_t {
-      if (dtype == RPCA_F32)
-        return launch_stream_f32(c.nb, mode, c.item_cnt, stream, descs, items_d + c.item_off);
-      return launch_stream_f64(c.nb, mode, c.item_cnt, stream, descs, items_d + c.item_off);
-    };
-    auto ev_begin = [&](int kind, int iter, int cls) {
-      if (!prof) return;
-      EvPair e;
-      e.kind = kind;
-      e.iter = iter;
-      e.cls = cls;
-      (void)hipEventCreate(&e.a);
-      (void)hipEventCreate(&e.b);
-      (void)hipEventRecord(e.a, stream);
-      evs.push_back(e);
-    };
-    auto ev_end = [&]() {
-      if (prof) (void)hipEventRecord(evs.back().b, stream);
-    };
-
-    CK(hipMemcpyAsync(arena, ctrl_h.data(), ctrl_bytes, hipMemcpyHostToDevice, stream));
-    for (size_t c = 0; c < classes.size(); ++c) {
-      ev_begin(0, 0, static_cast<int>(c));
-      CK(launch_class(classes[c], kModeInit));
-      ev_end();
-    }
-    CK(launch_reduce(ngroups, stream, descs, gitems_d));
-
-    int maxit_all = 0;
-    for (int i = 0; i < count; ++i) maxit_all = std::max(maxit_all, probs[i].maxit);
-    int launched = 0;
-    int chunk = kChunkFirst;
-    bool all_done = false;
-    while (!all_done) {
-      for (int c = 0; c < chunk; ++c) {
-        ++launched;
-        for (const auto& er : eig_runs) {
-          ev_begin(1, launched, -1);
-          CK(launch_eig(dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, stream, descs,
-                        ids_d + er.second.first));
-          ev_end();
-        }
-        for (size_t q = 0; q < classes.size(); ++q) {
-          ev_begin(2, launched, static_cast<int>(q));
-          CK(launch_class(classes[q], kModeUpdate));
-          ev_end();
-        }
-        CK(launch_reduce(ngroups, stream, descs, gitems_d));
+    int launched = 0;  // iterations enqueued (eigensolve launches per solve)
+    if (use_graph) {
+      CK(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+      {
+        hipError_t e = fork_lanes(L);
+        if (e == hipSuccess) e = enqueue_iterations(plan, L, kGraphChunk);
+        if (e == hipSuccess) e = join_lanes(L);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s0, &g);
+        graph = g;
+        CK(e);
+        CK(ee);
       }
-      CK(hipMemcpyAsync(st_h, arena + off_state, sizeof(SolveState) * count,
-                        hipMemcpyDeviceToHost, stream));
-      CK(hipStreamSynchronize(stream));
-      all_done = true;
-      for (int i = 0; i < count; ++i) all_done = all_done && st_h[i].done != 0;
-      if (!all_done && launched > maxit_all + 1) {
+      CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
+    auto run_chunk = [&](int chunk) -> hipError_t {
+      hipError_t e;
+      if (use_graph) {
+        e = hipGraphLaunch(gexec, s0);
+      } else {
+        e = fork_lanes(L);
+        if (e == hipSuccess) e = enqueue_iterations_at(plan, L, chunk, launched + 1);
+      }
+      launched += chunk;
+      return e;
+    };
+    int chunk = use_graph ? kGraphChunk : kDirectChunkFirst;
+    int slot = 0;
+    CK(run_chunk(chunk));
+    CK(enqueue_snapshot(plan, L, slot));
+    for (;;) {
+      const int prev = slot;
+      slot ^= 1;
+      if (!use_graph) chunk = std::min(chunk * 2, kDirectChunkMax);
+      const bool all_capped = launched > maxit_all + 1;
+      if (!all_capped) {
+        CK(run_chunk(chunk));
+        CK(enqueue_snapshot(plan, L, slot));
+      }
+      CK(hipEventSynchronize(L.snap[prev]));
+      bool all_done = true;
+      for (int i = 0; i < count; ++i) all_done = all_done && L.pinned[prev][i].done != 0;
+      if (all_done) break;
+      if (all_capped) {
+        // snapshot `prev` was taken after every launched iteration
         std::snprintf(g_last_error, sizeof(g_last_error),
-                      "a solve did not stop after %d eigensolve launches (cap %d)", launched,
-                      maxit_all);
-        rc = RPCA_ERR_DEVICE;  // the device failed to stop a solve by its cap
+                      "a solve did not stop after %d iterations (cap %d)", launched, maxit_all);
+        rc = RPCA_ERR_DEVICE;
         goto done;
       }
-      chunk = std::min(chunk * 2, kChunkMax);
     }
-    for (size_t c = 0; c < classes.size(); ++c) {
-      ev_begin(3, 0, static_cast<int>(c));
-      CK(launch_class(classes[c], kModeFinalize));
-      ev_end();
-    }
-    CK(hipMemcpyAsync(st_h, arena + off_state, sizeof(SolveState) * count,
-                      hipMemcpyDeviceToHost, stream));
-    CK(hipStreamSynchronize(stream));
-
+  }
+  CK(enqueue_finalize(plan, L));
+  CK(enqueue_snapshot(plan, L, 0));
+  CK(hipStreamSynchronize(s0));
+  {
     int worst_neg = 0, any_nc = 0;
     for (int i = 0; i < count; ++i) {
-      probs[i].iterations = st_h[i].iter;
-      probs[i].status = st_h[i].status;
-      probs[i].residual = st_h[i].resid;
-      if (st_h[i].status < 0) worst_neg = std::min(worst_neg, st_h[i].status);
-      if (st_h[i].status == RPCA_NOT_CONVERGED) any_nc = 1;
+      const SolveState& st = L.pinned[0][i];
+      recs[i].st = st;
+      probs[i].iterations = st.iter;
+      probs[i].status = st.status;
+      probs[i].residual = st.resid;
+      if (st.status < 0) worst_neg = std::min(worst_neg, st.status);
+      if (st.status == RPCA_NOT_CONVERGED) any_nc = 1;
     }
     rc = worst_neg < 0 ? worst_neg : (any_nc ? RPCA_NOT_CONVERGED : RPCA_OK);
+  }
 #ifdef RPCA_TRACE
-    trace_report(st_h[0], arena + base[0] + big[0].trace, geo[0].slots, stream);
+  trace_report(recs[0], s0);
 #endif
 
-    if (prof) {
-      double init_ms = 0, eig_ms = 0, upd_ms = 0, fin_ms = 0, upd_bytes = 0;
-      int64_t eig_n = 0, upd_n = 0, iters = 0;
-      int max_iter = 0;
-      for (int i = 0; i < count; ++i) {
-        max_iter = std::max(max_iter, st_h[i].iter);
-        iters += st_h[i].iter;
-      }
-      for (auto& e : evs) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e.a, e.b);
-        if (e.kind == 0) init_ms += ms;
-        else if (e.kind == 3) fin_ms += ms;
-        else if (e.kind == 1) {
-          if (e.iter <= max_iter) { eig_ms += ms; ++eig_n; }
-        } else {
-          double bytes = 0;
-          for (int s : classes[e.cls].solves) {
-            if (st_h[s].iter >= e.iter) {
-              const double words = e.iter == 1 ? 3.0 : 5.0;
-              bytes += words * static_cast<double>(probs[s].m) * static_cast<double>(probs[s].n) *
-                       static_cast<double>(geo[s].es);
-            }
+  if (prof) {
+    double init_ms = 0, eig_ms = 0, upd_ms = 0, fin_ms = 0, upd_bytes = 0;
+    int64_t eig_n = 0, upd_n = 0, iters = 0;
+    int max_iter = 0;
+    for (int i = 0; i < count; ++i) {
+      max_iter = std::max(max_iter, recs[i].st.iter);
+      iters += recs[i].st.iter;
+    }
+    for (auto& e : evs) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e.a, e.b);
+      if (e.kind == 0) {
+        init_ms += ms;
+      } else if (e.kind == 3) {
+        fin_ms += ms;
+      } else if (e.kind == 1) {
+        if (e.iter <= max_iter) {
+          eig_ms += ms;
+          ++eig_n;
+        }
+      } else {
+        const LaneRun& lr = plan.lanes[e.lane];
+        const int nb = lr.classes[e.cls].first;
+        double bytes = 0;
+        for (int i : lr.solves) {
+          if (recs[i].geo.nb == nb && recs[i].st.iter >= e.iter) {
+            const double words = e.iter == 1 ? 3.0 : 5.0;
+            bytes += words * static_cast<double>(recs[i].m) * recs[i].n * recs[i].geo.es;
           }
-          if (bytes > 0) { upd_ms += ms; ++upd_n; upd_bytes += bytes; }
+        }
+        if (bytes > 0) {
+          upd_ms += ms;
+          ++upd_n;
+          upd_bytes += bytes;
         }
       }
-      std::lock_guard<std::mutex> lk(g_prof.mu);
-      g_prof.init_ms += init_ms;
-      g_prof.eig_ms += eig_ms;
-      g_prof.update_ms += upd_ms;
-      g_prof.finalize_ms += fin_ms;
-      g_prof.eig_launches += eig_n;
-      g_prof.update_launches += upd_n;
-      g_prof.update_bytes += upd_bytes;
-      g_prof.solves += count;
-      g_prof.iterations += iters;
     }
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.init_ms += init_ms;
+    g_prof.eig_ms += eig_ms;
+    g_prof.update_ms += upd_ms;
+    g_prof.finalize_ms += fin_ms;
+    g_prof.eig_launches += eig_n;
+    g_prof.update_launches += upd_n;
+    g_prof.update_bytes += upd_bytes;
+    g_prof.solves += count;
+    g_prof.iterations += iters;
   }
 
 done:
+  t_evs = nullptr;
   for (auto& e : evs) {
     if (e.a) (void)hipEventDestroy(e.a);
     if (e.b) (void)hipEventDestroy(e.b);
   }
   if (rc == RPCA_ERR_DEVICE) (void)hipGetLastError();
-  (void)hipFreeAsync(arena, stream);
-  (void)hipStreamSynchronize(stream);
-  (void)hipHostFree(st_h);
+  for (auto s : L.s)
+    if (s) (void)hipStreamSynchronize(s);
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!L.s.empty()) {
+    plan_free(plan, L.s[0]);
+    if (arena) (void)hipFreeAsync(arena, L.s[0]);
+    (void)hipStreamSynchronize(L.s[0]);
+  }
+  lanes_destroy(L);
   return rc;
 }
 
+#undef CK
+
 }  // namespace
+
+const char* last_error_text() { return g_last_error; }
+
+bool profiling_enabled() { return profiling_on(); }
+
+}  // namespace rpca
+
+using namespace rpca;
 
 extern "C" {
 
@@ -524,8 +798,9 @@ size_t rpca_footprint_bytes(int64_t m, int64_t n, int32_t dtype) {
   Geo g;
   if (!geometry(m, n, dtype, g)) return 0;
   const Big b = big_layout(m, n, g);
-  return b.total + al256(sizeof(SolveDesc)) + al256(sizeof(SolveState)) +
-         al256(sizeof(GroupItem) * g.groups) + al256(sizeof(WorkItem) * g.slots) + 256;
+  // plus this solve's share of a control block
+  return b.total + al256(sizeof(SolveDesc) + sizeof(SolveState) + sizeof(int32_t)) +
+         al256(sizeof(GroupItem) * g.groups) + al256(sizeof(WorkItem) * g.slots);
 }
 
 const char* rpca_strerror(int code) {
@@ -541,7 +816,7 @@ const char* rpca_strerror(int code) {
   }
 }
 
-const char* rpca_version(void) { return "rpca_mi355x 0.1"; }
+const char* rpca_version(void) { return "rpca_mi355x 0.2"; }
 
 const char* rpca_last_error(void) { return g_last_error; }
 

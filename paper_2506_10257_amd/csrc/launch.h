@@ -19,6 +19,9 @@ hipError_t launch_stream_f64(int nb, int mode, int grid, hipStream_t stream,
                              const SolveDesc* descs, const WorkItem* items);
 hipError_t launch_reduce(int grid, hipStream_t stream, const SolveDesc* descs,
                          const GroupItem* items);
+hipError_t launch_gather_states(int count, hipStream_t stream, const SolveDesc* descs,
+                                SolveState* out);
+hipError_t launch_reset_states(int count, hipStream_t stream, const SolveDesc* descs);
 
 // Eigensolver classes 16, 32 and 64: the largest n each handles (256
 // threads each).  ids lists the solves (indices into descs) of the launch.

@@ -33,7 +33,38 @@ k_reduce_groups(const SolveDesc* __restrict__ descs, const GroupItem* __restrict
   }
 }
 
+// Copy the state of every solve of a plan to one contiguous array (read back
+// by the host with a single copy).
+__global__ void __launch_bounds__(64)
+k_gather_states(const SolveDesc* __restrict__ descs, int count, SolveState* __restrict__ out) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i < count) out[i] = *descs[i].st;
+}
+
+// Zero the state of every solve of a plan (done before its init pass).
+__global__ void __launch_bounds__(64)
+k_reset_states(const SolveDesc* __restrict__ descs, int count) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i < count) {
+    SolveState z{};
+    *descs[i].st = z;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_gather_states(int count, hipStream_t stream, const SolveDesc* descs,
+                                SolveState* out) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_states, dim3((count + 63) / 64), dim3(64), 0, stream, descs, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_states(int count, hipStream_t stream, const SolveDesc* descs) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reset_states, dim3((count + 63) / 64), dim3(64), 0, stream, descs, count);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce(int grid, hipStream_t stream, const SolveDesc* descs,
                          const GroupItem* items) {
