@@ -153,6 +153,23 @@ void rpca_profile_enable(int on);
 /* Copy the accumulated figures to *out; reset them when reset != 0. */
 int rpca_profile_read(rpca_profile* out, int reset);
 
+/*
+ * Tuning knobs (process-wide; they apply to calls started afterwards).
+ *
+ *   RPCA_KNOB_EIG_THREADS   threads per eigensolve workgroup for one
+ *                           eigensolver class (`cls` = 16, 32 or 64: the
+ *                           largest frame count of the class) and dtype:
+ *                           256, 512, or 1024 (classes 32 and 64 only).
+ *
+ * rpca_tune_set returns RPCA_OK, or RPCA_ERR_ARG for an unknown knob, class
+ * or value (the knob is then unchanged).  rpca_tune_get returns the current
+ * value, or RPCA_ERR_ARG.  The choice changes only speed: every variant
+ * computes the same arithmetic in the same order.
+ */
+#define RPCA_KNOB_EIG_THREADS 1
+int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value);
+int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls);
+
 /* Static description of a status code. */
 const char* rpca_strerror(int code);
 

@@ -21,11 +21,12 @@ from . import _lib
 from ._lib import (RPCA_OK, RPCA_NOT_CONVERGED, RPCA_ERR_ARG, RPCA_ERR_NOMEM,
                    RPCA_ERR_DEVICE, RPCA_ERR_NONFINITE, RPCA_ERR_UNSUPPORTED,
                    RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_GRAM_BF16X3, RPCA_N_MAX,
-                   RpcaProblem, RpcaProfile)
+                   RPCA_KNOB_EIG_THREADS, RpcaProblem, RpcaProfile)
 
 __all__ = ["solve", "solve_many", "SolveResult", "casorati_shape", "rpca_solve_f32",
            "rpca_solve_f64", "rpca_solve_many", "rpca_solve_ex", "rpca_footprint_bytes",
            "rpca_strerror", "rpca_version", "rpca_last_error", "rpca_profile_enable", "rpca_profile_read",
+           "rpca_tune_set", "rpca_tune_get", "RPCA_KNOB_EIG_THREADS",
            "RPCA_OK", "RPCA_NOT_CONVERGED", "RPCA_ERR_ARG", "RPCA_ERR_NOMEM",
            "RPCA_ERR_DEVICE", "RPCA_ERR_NONFINITE", "RPCA_ERR_UNSUPPORTED", "RPCA_F32",
            "RPCA_F64", "RPCA_GRAM_DEFAULT", "RPCA_GRAM_BF16X3", "RPCA_N_MAX"]
@@ -137,6 +138,14 @@ def rpca_profile_read(reset: bool = True) -> dict:
     p = RpcaProfile()
     _lib.load().rpca_profile_read(ctypes.byref(p), 1 if reset else 0)
     return {name: getattr(p, name) for name, _ in RpcaProfile._fields_}
+
+
+def rpca_tune_set(knob: int, dtype: int, cls: int, value: int) -> int:
+    return int(_lib.load().rpca_tune_set(int(knob), int(dtype), int(cls), int(value)))
+
+
+def rpca_tune_get(knob: int, dtype: int, cls: int) -> int:
+    return int(_lib.load().rpca_tune_get(int(knob), int(dtype), int(cls)))
 
 
 @dataclass

@@ -23,11 +23,13 @@ RPCA_F32 = 1
 RPCA_GRAM_DEFAULT = 0
 RPCA_GRAM_BF16X3 = 1
 RPCA_N_MAX = 128
+RPCA_KNOB_EIG_THREADS = 1
 
 EXPORTS = (
     "rpca_solve_f64", "rpca_solve_f32", "rpca_solve_many", "rpca_solve_ex",
     "rpca_footprint_bytes", "rpca_strerror", "rpca_version",
     "rpca_profile_enable", "rpca_profile_read", "rpca_last_error",
+    "rpca_tune_set", "rpca_tune_get",
 )
 
 
@@ -103,5 +105,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpca_profile_enable.restype = None
     lib.rpca_profile_read.argtypes = [ctypes.POINTER(RpcaProfile), ctypes.c_int]
     lib.rpca_profile_read.restype = ctypes.c_int
+    lib.rpca_tune_set.argtypes = [i32, i32, i32, i32]
+    lib.rpca_tune_set.restype = ctypes.c_int
+    lib.rpca_tune_get.argtypes = [i32, i32, i32]
+    lib.rpca_tune_get.restype = ctypes.c_int
     _lib = lib
     return lib

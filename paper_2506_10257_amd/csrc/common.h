@@ -14,7 +14,6 @@ constexpr int kThreads = 256;      // threads per streaming workgroup
 constexpr int kTile = 256;         // pixel rows per tile: one row per thread
 constexpr int kGroup = 32;         // partial slots per first-level reduction group
 constexpr int kEigMaxN = 64;       // frame count handled by the LDS eigensolver
-constexpr int kEigThreads = 256;
 constexpr int kScalars = 4;        // scalar slots at the head of each partial
 
 // Status codes (mirrors include/rpca.h).

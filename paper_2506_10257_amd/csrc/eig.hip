@@ -30,6 +30,7 @@
 // d = g_qq - g_pp, c = 1/sqrt(1 + t^2), s = t c.  A pair is rotated while
 // g_pq^2 > eps^2 |g_pp g_qq| (relative off-diagonal test); eps is 1e-15 for
 // FP64 solves and 1e-11 for FP32 solves, whose data carry 6e-8 rounding.
+#include <atomic>
 #include <type_traits>
 
 #include "common.h"
@@ -494,26 +495,52 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
 
 int eig_class(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= kEigMaxN ? 64 : 0)); }
 
+namespace {
+// Threads per eigensolve workgroup, per [dtype][class 16/32/64].  Defaults
+// from timing on MI355X: a round's work is spread over more waves as n grows.
+std::atomic<int> g_eig_nt[2][3] = {{{256}, {512}, {1024}}, {{256}, {512}, {1024}}};
+int cls_index(int ncls) { return ncls == 16 ? 0 : (ncls == 32 ? 1 : (ncls == 64 ? 2 : -1)); }
+}  // namespace
+
+bool eig_threads_valid(int ncls, int nt) {
+  if (cls_index(ncls) < 0) return false;
+  return nt == 256 || nt == 512 || (nt == 1024 && ncls >= 32);
+}
+
+int eig_threads(int dtype, int ncls) {
+  const int c = cls_index(ncls);
+  return c < 0 ? 0 : g_eig_nt[dtype == 0 ? 0 : 1][c].load(std::memory_order_relaxed);
+}
+
+bool set_eig_threads(int dtype, int ncls, int nt) {
+  if (!eig_threads_valid(ncls, nt)) return false;
+  g_eig_nt[dtype == 0 ? 0 : 1][cls_index(ncls)].store(nt, std::memory_order_relaxed);
+  return true;
+}
+
 hipError_t launch_eig(int dtype, int ncls, int grid, hipStream_t stream, const SolveDesc* descs,
                       const int32_t* ids) {
   if (grid <= 0) return hipSuccess;
-  const dim3 g(grid), b(kEigThreads);
-#define RPCA_EIG_CASE(N)                                                                  \
-  case N:                                                                                 \
-    if (dtype == 0)                                                                       \
-      hipLaunchKernelGGL((k_eig<double, N, kEigThreads>), g, b, 0, stream, descs, ids);   \
-    else                                                                                  \
-      hipLaunchKernelGGL((k_eig<float, N, kEigThreads>), g, b, 0, stream, descs, ids);    \
-    break;
-  switch (ncls) {
-    RPCA_EIG_CASE(16)
-    RPCA_EIG_CASE(32)
-    RPCA_EIG_CASE(64)
-    default:
-      return hipErrorInvalidValue;
+  const int nt = eig_threads(dtype, ncls);
+  const dim3 g(grid), b(nt);
+#define RPCA_EIG_CASE(N, NT)                                                  \
+  if (ncls == N && nt == NT) {                                                \
+    if (dtype == 0)                                                           \
+      hipLaunchKernelGGL((k_eig<double, N, NT>), g, b, 0, stream, descs, ids); \
+    else                                                                      \
+      hipLaunchKernelGGL((k_eig<float, N, NT>), g, b, 0, stream, descs, ids);  \
+    return hipGetLastError();                                                 \
   }
+  RPCA_EIG_CASE(16, 256)
+  RPCA_EIG_CASE(16, 512)
+  RPCA_EIG_CASE(32, 256)
+  RPCA_EIG_CASE(32, 512)
+  RPCA_EIG_CASE(32, 1024)
+  RPCA_EIG_CASE(64, 256)
+  RPCA_EIG_CASE(64, 512)
+  RPCA_EIG_CASE(64, 1024)
 #undef RPCA_EIG_CASE
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace rpca

@@ -15,8 +15,8 @@
 //     overlaps device work; a solve that has finished makes its later
 //     launches exit at once;
 //   * runs the finalize pass, reads the states back and frees the memory.
-// With kernel timing enabled the chunk is launched directly (no graph) with
-// HIP events around every launch.
+// With kernel timing enabled everything runs on one lane, launched directly
+// (no graph) with HIP events around every launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -514,8 +514,10 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
     r.maxit = p.maxit;
   }
 
-  // Lanes: balance the matrix sizes, largest first.
-  const int nlanes = std::min(count, kMaxLanes);
+  // Lanes: balance the matrix sizes, largest first.  Kernel timing runs on
+  // one lane so that each launch's event pair brackets that launch alone.
+  const bool prof = profiling_on();
+  const int nlanes = prof ? 1 : std::min(count, kMaxLanes);
   {
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
@@ -541,7 +543,6 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   }
   setup_pool(dev);
 
-  const bool prof = profiling_on();
   const bool use_graph = !prof && !graphs_disabled();
   int rc = RPCA_OK;
   char* arena = nullptr;
@@ -816,7 +817,22 @@ const char* rpca_strerror(int code) {
   }
 }
 
-const char* rpca_version(void) { return "rpca_mi355x 0.2"; }
+const char* rpca_version(void) { return "rpca_mi355x 0.3"; }
+
+int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value) {
+  if (dtype != RPCA_F32 && dtype != RPCA_F64) return RPCA_ERR_ARG;
+  if (knob == RPCA_KNOB_EIG_THREADS) return set_eig_threads(dtype, cls, value) ? RPCA_OK : RPCA_ERR_ARG;
+  return RPCA_ERR_ARG;
+}
+
+int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls) {
+  if (dtype != RPCA_F32 && dtype != RPCA_F64) return RPCA_ERR_ARG;
+  if (knob == RPCA_KNOB_EIG_THREADS) {
+    const int v = eig_threads(dtype, cls);
+    return v > 0 ? v : RPCA_ERR_ARG;
+  }
+  return RPCA_ERR_ARG;
+}
 
 const char* rpca_last_error(void) { return g_last_error; }
 

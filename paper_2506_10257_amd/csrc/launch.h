@@ -23,9 +23,13 @@ hipError_t launch_gather_states(int count, hipStream_t stream, const SolveDesc* 
                                 SolveState* out);
 hipError_t launch_reset_states(int count, hipStream_t stream, const SolveDesc* descs);
 
-// Eigensolver classes 16, 32 and 64: the largest n each handles (256
-// threads each).  ids lists the solves (indices into descs) of the launch.
+// Eigensolver classes 16, 32 and 64: the largest n each handles.  The
+// workgroup size of each class (256, 512 or 1024 threads) is a tuning knob.
+// ids lists the solves (indices into descs) of the launch.
 int eig_class(int n);
+bool eig_threads_valid(int ncls, int nt);
+int eig_threads(int dtype, int ncls);
+bool set_eig_threads(int dtype, int ncls, int nt);
 hipError_t launch_eig(int dtype, int ncls, int grid, hipStream_t stream, const SolveDesc* descs,
                       const int32_t* ids);
 

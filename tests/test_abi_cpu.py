@@ -88,3 +88,23 @@ def test_batch_argument_checks(lib):
     assert lib.rpca_solve_many(arr, 1, 5, 0, None) == _lib.RPCA_ERR_ARG
     assert lib.rpca_solve_many(arr, 1, _lib.RPCA_F32, 9, None) == _lib.RPCA_ERR_ARG
     assert lib.rpca_solve_many(arr, 1, _lib.RPCA_F32, 0, None) == _lib.RPCA_ERR_ARG  # NULL M
+
+
+def test_tuning_knobs(lib):
+    import paper_2506_10257_amd as rp
+    K = rp.RPCA_KNOB_EIG_THREADS
+    for dt in (rp.RPCA_F32, rp.RPCA_F64):
+        for cls in (16, 32, 64):
+            assert rp.rpca_tune_get(K, dt, cls) in (256, 512, 1024)
+    old = rp.rpca_tune_get(K, rp.RPCA_F32, 64)
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 64, 512) == rp.RPCA_OK
+    assert rp.rpca_tune_get(K, rp.RPCA_F32, 64) == 512
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 64, old) == rp.RPCA_OK
+    # invalid class, value, dtype and knob leave the table unchanged
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 24, 256) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 16, 1024) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 32, 300) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_set(K, 7, 32, 256) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_set(99, rp.RPCA_F32, 32, 256) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_get(99, rp.RPCA_F32, 32) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_get(K, rp.RPCA_F32, 64) == old
