@@ -170,6 +170,72 @@ int rpca_profile_read(rpca_profile* out, int reset);
 int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value);
 int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls);
 
+/*
+ * ---- serving: continuous batching of arriving windows ------------------
+ *
+ * The paper targets real-time filtering of streamed frame windows (Abstract;
+ * Sec. IV, discussion of run time and of further GPU optimisation).  A server
+ * takes windows of different sizes and frame counts as they arrive and runs
+ * them together:
+ *
+ *   rpca_server_submit  queues a request (FIFO).  The problem's M, L and S
+ *                       (device) must stay valid until its completion is
+ *                       reported; lambda, mu, tol and maxit as for a solve.
+ *                       Returns RPCA_ERR_ARG / RPCA_ERR_UNSUPPORTED for a
+ *                       problem a solve would reject (nothing is queued).
+ *   rpca_server_step    admits queued requests in arrival order while fewer
+ *                       than max_active solves are active and the active
+ *                       requests' footprint (rpca_server_request_bytes: the
+ *                       library workspace plus M, L and S) fits hbm_budget.
+ *                       The head of the queue waits for room; a request
+ *                       larger than the whole budget completes at once with
+ *                       RPCA_ERR_NOMEM.  Newly admitted requests get their
+ *                       device workspace, which holds their S, Y,
+ *                       eigenvectors and state until they finish.  Then
+ *                       `quantum` iterations of every active solve run
+ *                       together on the device, and the solves that stopped
+ *                       are finalized (L and S written, workspace freed).
+ *                       Up to `capacity` completions are copied to out[] and
+ *                       their number to *count; further completions wait for
+ *                       the next call.  L and S of a reported completion are
+ *                       final.  Returns RPCA_OK, or RPCA_ERR_DEVICE /
+ *                       RPCA_ERR_NOMEM when the device failed (after a
+ *                       device error every later step fails too).
+ *   rpca_server_pending queued and active counts and the admitted bytes;
+ *                       returns the number of requests not yet reported.
+ *
+ * Each result is bitwise identical to the same problem solved alone.  The
+ * calls are serialised by a lock; the stream argument of create is the stream
+ * on which the caller produces M (it is synchronised before admission).
+ * flags: 0, or RPCA_SERVER_SIMULATE to run the admission logic without any
+ * device work (every request then completes after maxit iterations with
+ * RPCA_NOT_CONVERGED and residual 0).  create returns NULL for an invalid
+ * argument (dtype, gram_mode other than RPCA_GRAM_DEFAULT, a zero budget,
+ * max_active < 1, quantum < 1, unknown flags).
+ */
+typedef struct rpca_server rpca_server;
+typedef struct rpca_completion {
+    int64_t tag;          /* the tag given to rpca_server_submit */
+    int32_t status;       /* as a solve's return code */
+    int32_t iterations;
+    double residual;      /* ||M - L - S||_F / ||M||_F */
+} rpca_completion;
+
+#define RPCA_SERVER_SIMULATE 1
+
+rpca_server* rpca_server_create(int32_t dtype, int32_t gram_mode, size_t hbm_budget,
+                                int32_t max_active, int32_t quantum, int32_t flags,
+                                void* stream);
+int rpca_server_submit(rpca_server* s, const rpca_problem* p, int64_t tag);
+int rpca_server_step(rpca_server* s, rpca_completion* out, int32_t capacity, int32_t* count);
+int rpca_server_pending(rpca_server* s, int32_t* queued, int32_t* active, size_t* bytes_in_use);
+/* Largest admitted footprint seen so far (bytes). */
+size_t rpca_server_peak_bytes(rpca_server* s);
+/* Admission footprint of one request: workspace + M, L and S. 0 if unsupported. */
+size_t rpca_server_request_bytes(int64_t m, int64_t n, int32_t dtype);
+/* Wait for device work, free every workspace and drop queued requests. */
+void rpca_server_destroy(rpca_server* s);
+
 /* Static description of a status code. */
 const char* rpca_strerror(int code);
 

@@ -24,12 +24,15 @@ RPCA_GRAM_DEFAULT = 0
 RPCA_GRAM_BF16X3 = 1
 RPCA_N_MAX = 128
 RPCA_KNOB_EIG_THREADS = 1
+RPCA_SERVER_SIMULATE = 1
 
 EXPORTS = (
     "rpca_solve_f64", "rpca_solve_f32", "rpca_solve_many", "rpca_solve_ex",
     "rpca_footprint_bytes", "rpca_strerror", "rpca_version",
     "rpca_profile_enable", "rpca_profile_read", "rpca_last_error",
     "rpca_tune_set", "rpca_tune_get",
+    "rpca_server_create", "rpca_server_submit", "rpca_server_step", "rpca_server_pending",
+    "rpca_server_peak_bytes", "rpca_server_request_bytes", "rpca_server_destroy",
 )
 
 
@@ -61,6 +64,15 @@ class RpcaProfile(ctypes.Structure):
         ("update_bytes", ctypes.c_double),
         ("solves", ctypes.c_int64),
         ("iterations", ctypes.c_int64),
+    ]
+
+
+class RpcaCompletion(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("residual", ctypes.c_double),
     ]
 
 
@@ -109,5 +121,20 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpca_tune_set.restype = ctypes.c_int
     lib.rpca_tune_get.argtypes = [i32, i32, i32]
     lib.rpca_tune_get.restype = ctypes.c_int
+    sz = ctypes.c_size_t
+    lib.rpca_server_create.argtypes = [i32, i32, sz, i32, i32, i32, vp]
+    lib.rpca_server_create.restype = vp
+    lib.rpca_server_submit.argtypes = [vp, ctypes.POINTER(RpcaProblem), i64]
+    lib.rpca_server_submit.restype = ctypes.c_int
+    lib.rpca_server_step.argtypes = [vp, ctypes.POINTER(RpcaCompletion), i32, ctypes.POINTER(i32)]
+    lib.rpca_server_step.restype = ctypes.c_int
+    lib.rpca_server_pending.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
+    lib.rpca_server_pending.restype = ctypes.c_int
+    lib.rpca_server_peak_bytes.argtypes = [vp]
+    lib.rpca_server_peak_bytes.restype = sz
+    lib.rpca_server_request_bytes.argtypes = [i64, i64, i32]
+    lib.rpca_server_request_bytes.restype = sz
+    lib.rpca_server_destroy.argtypes = [vp]
+    lib.rpca_server_destroy.restype = None
     _lib = lib
     return lib

@@ -102,6 +102,16 @@ hipError_t enqueue_finalize(const Plan& plan, const Lanes& L);
 // buffer `slot` and record snap[slot].
 hipError_t enqueue_snapshot(const Plan& plan, Lanes& L, int slot);
 
+// Validate one problem and fill its record (parameters, geometry, layout).
+// Returns RPCA_OK, RPCA_ERR_ARG or RPCA_ERR_UNSUPPORTED.
+int make_rec(const rpca_problem& p, int dtype, SolveRec& r);
+// Spread solves over lanes, balancing m*n, largest first (stable).
+void assign_lanes(std::vector<SolveRec*>& recs, int nlanes);
+// Memory pool of the device: keep freed blocks cached (set once per device).
+void setup_pool(int dev);
+bool graphs_disabled();
+constexpr int kMaxLanes = 3;
+
 void set_error(const char* what, hipError_t e);
 void set_error_text(const char* text);
 

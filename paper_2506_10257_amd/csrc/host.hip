@@ -41,7 +41,6 @@ namespace {
 constexpr int kGraphChunk = 16;
 constexpr int kDirectChunkFirst = 8;
 constexpr int kDirectChunkMax = 64;
-constexpr int kMaxLanes = 3;
 
 size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -88,8 +87,13 @@ void ev_end(hipStream_t s) {
   if (t_evs) (void)hipEventRecord(t_evs->back().b, s);
 }
 
+}  // namespace
+
 // ------------------------------------------------------------- device pool
+namespace {
 std::once_flag g_pool_once[64];
+}  // namespace
+
 void setup_pool(int dev) {
   if (dev < 0 || dev >= 64) return;
   std::call_once(g_pool_once[dev], [dev] {
@@ -100,6 +104,13 @@ void setup_pool(int dev) {
     }
   });
 }
+
+bool graphs_disabled() {
+  const char* v = std::getenv("RPCA_NO_GRAPH");
+  return v && v[0] && v[0] != '0';
+}
+
+namespace {
 
 bool overlap(const void* a, const void* b, size_t bytes) {
   const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
@@ -466,6 +477,41 @@ hipError_t enqueue_snapshot(const Plan& plan, Lanes& L, int slot) {
 
 #undef EQ
 
+int make_rec(const rpca_problem& p, int dtype, SolveRec& r) {
+  if (!p.M || !p.L || !p.S || p.m < 1 || p.n < 1 || p.n > RPCA_N_MAX || p.maxit < 1)
+    return RPCA_ERR_ARG;
+  if (!std::isfinite(p.lambda) || !std::isfinite(p.mu) || std::isnan(p.tol)) return RPCA_ERR_ARG;
+  const size_t bytes = static_cast<size_t>(p.m) * static_cast<size_t>(p.n) * (dtype == RPCA_F32 ? 4 : 8);
+  if (overlap(p.M, p.L, bytes) || overlap(p.M, p.S, bytes) || overlap(p.L, p.S, bytes))
+    return RPCA_ERR_ARG;
+  if (!geometry(p.m, p.n, dtype, r.geo)) return RPCA_ERR_UNSUPPORTED;
+  r.big = big_layout(p.m, p.n, r.geo);
+  r.M = p.M;
+  r.L = p.L;
+  r.S = p.S;
+  r.m = p.m;
+  r.n = static_cast<int32_t>(p.n);
+  r.lam = p.lambda;
+  r.mu = p.mu;
+  r.tol = p.tol;
+  r.maxit = p.maxit;
+  return RPCA_OK;
+}
+
+void assign_lanes(std::vector<SolveRec*>& recs, int nlanes) {
+  std::vector<int> order(recs.size());
+  for (size_t i = 0; i < recs.size(); ++i) order[i] = static_cast<int>(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return recs[a]->m * recs[a]->n > recs[b]->m * recs[b]->n;
+  });
+  std::vector<double> load(nlanes, 0.0);
+  for (int i : order) {
+    const int l = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    recs[i]->lane = l;
+    load[l] += static_cast<double>(recs[i]->m) * recs[i]->n;
+  }
+}
+
 // ---------------------------------------------------------------- run_batch
 namespace {
 
@@ -479,11 +525,6 @@ namespace {
     }                                             \
   } while (0)
 
-bool graphs_disabled() {
-  const char* v = std::getenv("RPCA_NO_GRAPH");
-  return v && v[0] && v[0] != '0';
-}
-
 int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStream_t user) {
   g_last_error[0] = '\0';
   if (count < 1 || probs == nullptr) return RPCA_ERR_ARG;
@@ -493,44 +534,14 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
 
   std::vector<SolveRec> recs(count);
   for (int i = 0; i < count; ++i) {
-    rpca_problem& p = probs[i];
-    if (!p.M || !p.L || !p.S || p.m < 1 || p.n < 1 || p.n > RPCA_N_MAX || p.maxit < 1)
-      return RPCA_ERR_ARG;
-    if (!std::isfinite(p.lambda) || !std::isfinite(p.mu) || std::isnan(p.tol)) return RPCA_ERR_ARG;
-    const size_t bytes = static_cast<size_t>(p.m) * static_cast<size_t>(p.n) * (dtype == RPCA_F32 ? 4 : 8);
-    if (overlap(p.M, p.L, bytes) || overlap(p.M, p.S, bytes) || overlap(p.L, p.S, bytes))
-      return RPCA_ERR_ARG;
-    SolveRec& r = recs[i];
-    if (!geometry(p.m, p.n, dtype, r.geo)) return RPCA_ERR_UNSUPPORTED;
-    r.big = big_layout(p.m, p.n, r.geo);
-    r.M = p.M;
-    r.L = p.L;
-    r.S = p.S;
-    r.m = p.m;
-    r.n = static_cast<int32_t>(p.n);
-    r.lam = p.lambda;
-    r.mu = p.mu;
-    r.tol = p.tol;
-    r.maxit = p.maxit;
+    const int vrc = make_rec(probs[i], dtype, recs[i]);
+    if (vrc != RPCA_OK) return vrc;
   }
 
   // Lanes: balance the matrix sizes, largest first.  Kernel timing runs on
   // one lane so that each launch's event pair brackets that launch alone.
   const bool prof = profiling_on();
   const int nlanes = prof ? 1 : std::min(count, kMaxLanes);
-  {
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int a, int b) {
-      return recs[a].m * recs[a].n > recs[b].m * recs[b].n;
-    });
-    std::vector<double> load(nlanes, 0.0);
-    for (int i : order) {
-      const int l = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
-      recs[i].lane = l;
-      load[l] += static_cast<double>(recs[i].m) * recs[i].n;
-    }
-  }
 
   int dev = 0;
   (void)hipGetLastError();  // launches below report through the per-thread last error
@@ -557,6 +568,7 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
     ptrs[i] = &recs[i];
     maxit_all = std::max(maxit_all, recs[i].maxit);
   }
+  assign_lanes(ptrs, nlanes);
 
   rc = lanes_create(L, nlanes);
   if (rc != RPCA_OK) {

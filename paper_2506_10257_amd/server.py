@@ -1,0 +1,110 @@
+"""Python binding of the continuous-batching server (rpca_server_* in
+include/rpca.h).  Argument marshalling only: admission, scheduling and every
+iteration run in the library.
+
+    srv = Server(dtype=RPCA_F32, hbm_budget=64 << 30, max_active=64, quantum=16)
+    srv.submit(M, tag=7, tol=1e-6, maxit=1000)   # M: device Casorati tensor
+    for c in srv.step():                         # one quantum of iterations
+        c.tag, c.status, c.iterations, c.L, c.S
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+from . import _lib
+from ._lib import RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_SERVER_SIMULATE, RpcaCompletion
+
+
+@dataclass
+class Completion:
+    tag: int
+    status: int
+    iterations: int
+    residual: float
+    L: object = None
+    S: object = None
+
+
+def request_bytes(m: int, n: int, dtype: int) -> int:
+    """Admission footprint of one request (workspace + M, L and S)."""
+    return int(_lib.load().rpca_server_request_bytes(int(m), int(n), int(dtype)))
+
+
+class Server:
+    """Requests are admitted FIFO by footprint; each step runs `quantum`
+    iterations of every active solve together on the device."""
+
+    def __init__(self, dtype: int = RPCA_F32, hbm_budget: int = 64 << 30, max_active: int = 64,
+                 quantum: int = 16, simulate: bool = False, stream: Optional[int] = None):
+        lib = _lib.load()
+        if stream is None and not simulate:
+            import torch
+            stream = int(torch.cuda.current_stream().cuda_stream)
+        self._lib = lib
+        self._dtype = int(dtype)
+        self._h = lib.rpca_server_create(self._dtype, RPCA_GRAM_DEFAULT, int(hbm_budget),
+                                         int(max_active), int(quantum),
+                                         RPCA_SERVER_SIMULATE if simulate else 0, stream or 0)
+        if not self._h:
+            raise ValueError("rpca_server_create rejected the arguments")
+        self._cap = max(int(max_active), 1) * 4
+        self._buf = (RpcaCompletion * self._cap)()
+        self._live = {}  # tag -> (M, L, S) kept alive until completion
+
+    def submit_raw(self, problem, tag: int, keep=None) -> int:
+        """Queue an rpca_problem whose device buffers the caller owns."""
+        rc = self._lib.rpca_server_submit(self._h, ctypes.byref(problem), int(tag))
+        if rc == 0:
+            self._live[int(tag)] = keep
+        return int(rc)
+
+    def submit(self, M, tag: int, lam: Optional[float] = None, mu: Optional[float] = None,
+               tol: float = 1e-6, maxit: int = 1000) -> None:
+        """Queue a solve of the device tensor M; L and S are allocated here and
+        returned with the completion."""
+        import torch
+        from . import _problem
+        L = torch.empty_like(M)
+        S = torch.empty_like(M)
+        p = _problem(M, L, S, lam, mu, tol, maxit)
+        rc = self.submit_raw(p, tag, keep=(M, L, S))
+        if rc != 0:
+            raise ValueError(f"request rejected: {rc}")
+
+    def step(self) -> list:
+        n = ctypes.c_int32(0)
+        rc = self._lib.rpca_server_step(self._h, self._buf, self._cap, ctypes.byref(n))
+        out = []
+        for i in range(n.value):
+            c = self._buf[i]
+            keep = self._live.pop(int(c.tag), None)
+            L = S = None
+            if keep is not None and len(keep) == 3:
+                L, S = keep[1], keep[2]
+            out.append(Completion(int(c.tag), int(c.status), int(c.iterations), float(c.residual), L, S))
+        if rc < 0:
+            raise RuntimeError(f"server step failed ({rc}): {self._lib.rpca_last_error().decode()}")
+        return out
+
+    def pending(self) -> tuple[int, int, int, int]:
+        """(not yet reported, queued, active, admitted bytes)."""
+        q, a, b = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_size_t(0)
+        left = self._lib.rpca_server_pending(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(b))
+        return int(left), int(q.value), int(a.value), int(b.value)
+
+    def peak_bytes(self) -> int:
+        return int(self._lib.rpca_server_peak_bytes(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            self._lib.rpca_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,105 @@
+"""Admission and retirement logic of the serving loop, run without a device
+(RPCA_SERVER_SIMULATE: no HIP call is made; a request finishes after maxit
+iterations counted in quanta)."""
+import pytest
+
+import paper_2506_10257_amd as rp
+from paper_2506_10257_amd import _lib
+from paper_2506_10257_amd.server import Server, request_bytes
+
+
+def _prob(m, n, maxit, base):
+    """Problem with placeholder device addresses (never dereferenced here)."""
+    p = _lib.RpcaProblem()
+    span = m * n * 4
+    p.M, p.L, p.S = base, base + 2 * span, base + 4 * span
+    p.m, p.n = m, n
+    p.lam, p.mu, p.tol, p.maxit = -1.0, -1.0, 1e-6, maxit
+    return p
+
+
+def _drain(srv, max_steps=1000):
+    order, trace = [], []
+    for _ in range(max_steps):
+        left, q, a, used = srv.pending()
+        if left == 0:
+            break
+        trace.append((q, a, used))
+        order += [(c.tag, c.status, c.iterations) for c in srv.step()]
+    return order, trace
+
+
+def test_fifo_and_max_active():
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=2, quantum=16, simulate=True)
+    for t in range(6):
+        assert srv.submit_raw(_prob(4096, 20, 32, (t + 1) << 32), t) == 0
+    order, trace = _drain(srv)
+    assert [t for t, _, _ in order] == list(range(6))
+    assert all(st == rp.RPCA_NOT_CONVERGED and it == 32 for _, st, it in order)
+    assert max(a for _, a, _ in trace) <= 2
+    srv.close()
+
+
+def test_budget_and_head_of_line():
+    big = request_bytes(65536, 40, rp.RPCA_F32)
+    small = request_bytes(4096, 10, rp.RPCA_F32)
+    assert big > 2 * small > 0
+    srv = Server(rp.RPCA_F32, hbm_budget=big, max_active=8, quantum=10, simulate=True)
+    srv.submit_raw(_prob(65536, 40, 30, 1 << 36), 0)  # needs 3 steps
+    srv.submit_raw(_prob(4096, 10, 10, 2 << 36), 1)
+    srv.submit_raw(_prob(4096, 10, 10, 3 << 36), 2)
+    order, trace = _drain(srv)
+    # the small requests do not overtake the big one at the head of the queue
+    assert [t for t, _, _ in order] == [0, 1, 2]
+    assert srv.peak_bytes() <= big
+    assert all(used <= big for _, _, used in trace)
+    srv.close()
+
+
+def test_oversized_request_rejected_with_nomem():
+    small = request_bytes(4096, 10, rp.RPCA_F32)
+    srv = Server(rp.RPCA_F32, hbm_budget=small, max_active=4, quantum=8, simulate=True)
+    srv.submit_raw(_prob(65536, 40, 8, 1 << 36), 5)
+    srv.submit_raw(_prob(4096, 10, 8, 2 << 36), 6)
+    order, _ = _drain(srv)
+    assert order[0] == (5, rp.RPCA_ERR_NOMEM, 0)
+    assert order[1][0] == 6 and order[1][1] == rp.RPCA_NOT_CONVERGED
+    srv.close()
+
+
+def test_continuous_admission():
+    """A request submitted while others run joins without waiting for them."""
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=4, quantum=10, simulate=True)
+    srv.submit_raw(_prob(4096, 20, 100, 1 << 36), 0)  # 10 steps
+    srv.step()
+    srv.step()
+    srv.submit_raw(_prob(4096, 20, 20, 2 << 36), 1)  # 2 steps
+    assert srv.pending()[2] == 1
+    got = srv.step()
+    assert got == [] and srv.pending()[2] == 2
+    got = srv.step()
+    assert [c.tag for c in got] == [1]
+    order, _ = _drain(srv)
+    assert [t for t, _, _ in order] == [0]
+    srv.close()
+
+
+def test_submit_rejects_what_a_solve_rejects():
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 30, max_active=2, quantum=4, simulate=True)
+    assert srv.submit_raw(_prob(4096, 0, 10, 1 << 36), 0) == rp.RPCA_ERR_ARG
+    assert srv.submit_raw(_prob(4096, rp.RPCA_N_MAX + 1, 10, 1 << 36), 0) == rp.RPCA_ERR_ARG
+    assert srv.submit_raw(_prob(4096, 10, 0, 1 << 36), 0) == rp.RPCA_ERR_ARG
+    p = _prob(4096, 10, 10, 1 << 36)
+    p.S = p.M  # aliasing
+    assert srv.submit_raw(p, 0) == rp.RPCA_ERR_ARG
+    assert srv.pending()[0] == 0
+    srv.close()
+
+
+@pytest.mark.parametrize("args", [
+    dict(dtype=7), dict(hbm_budget=0), dict(max_active=0), dict(quantum=0)])
+def test_create_rejects_bad_arguments(args):
+    kw = dict(dtype=rp.RPCA_F32, hbm_budget=1 << 30, max_active=2, quantum=4, simulate=True)
+    kw.update(args)
+    with pytest.raises(ValueError):
+        Server(**kw)
