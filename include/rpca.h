@@ -63,10 +63,16 @@ extern "C" {
 #define RPCA_GRAM_DEFAULT 0  /* Gram and rebuild in the storage precision,
                                 Gram accumulated in FP64                      */
 #define RPCA_GRAM_BF16X3  1  /* F32 only: Gram and rebuild as split-BF16
-                                products (hi*hi + hi*lo + lo*hi) on MFMA with
-                                FP32 accumulation; eigensolve stays FP64      */
+                                products (hi*hi + hi*lo + lo*hi, x = hi + lo)
+                                on MFMA with FP32 accumulation (the Gram in
+                                FP32 over 64-row tiles, FP64 across tiles);
+                                eigensolve and thresholding stay FP64.  Less
+                                accurate than the default: see the stated
+                                error of each result                         */
 
-#define RPCA_N_MAX 128   /* largest frame count n accepted                    */
+#define RPCA_N_MAX 112   /* largest frame count n accepted (the FP64 eigensolve
+                            of the n x n Gram keeps G and V in 160 KB of LDS);
+                            RPCA_F64 solves accept n <= 32                   */
 
 /*
  * rpca_solve_f64 / rpca_solve_f32 - one RPCA solve.
@@ -163,10 +169,21 @@ int rpca_profile_read(rpca_profile* out, int reset);
  *
  * rpca_tune_set returns RPCA_OK, or RPCA_ERR_ARG for an unknown knob, class
  * or value (the knob is then unchanged).  rpca_tune_get returns the current
- * value, or RPCA_ERR_ARG.  The choice changes only speed: every variant
- * computes the same arithmetic in the same order.
+ * value, or RPCA_ERR_ARG.  The eigensolver sizes change only speed: every
+ * variant computes the same arithmetic in the same order.
  */
 #define RPCA_KNOB_EIG_THREADS 1
+/*   RPCA_KNOB_STREAM_KERNEL streaming kernel of one FP32 frame class (`cls` =
+ *                           4, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 56, 60
+ *                           or 64, the register classes; dtype RPCA_F32):
+ *                           0 = one thread per pixel row with the frames in
+ *                           registers (VALU contractions), 1 = 64-row tiles
+ *                           staged in LDS with MFMA contractions.  Windows of
+ *                           more than 64 frames always use the tile kernel.
+ *                           The two kernels round differently (both within
+ *                           the FP32 bar); a solve's result never depends on
+ *                           what else runs with it.                          */
+#define RPCA_KNOB_STREAM_KERNEL 2
 int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value);
 int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls);
 

@@ -21,12 +21,12 @@ from . import _lib
 from ._lib import (RPCA_OK, RPCA_NOT_CONVERGED, RPCA_ERR_ARG, RPCA_ERR_NOMEM,
                    RPCA_ERR_DEVICE, RPCA_ERR_NONFINITE, RPCA_ERR_UNSUPPORTED,
                    RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_GRAM_BF16X3, RPCA_N_MAX,
-                   RPCA_KNOB_EIG_THREADS, RpcaProblem, RpcaProfile)
+                   RPCA_KNOB_EIG_THREADS, RPCA_KNOB_STREAM_KERNEL, RpcaProblem, RpcaProfile)
 
 __all__ = ["solve", "solve_many", "SolveResult", "casorati_shape", "rpca_solve_f32",
            "rpca_solve_f64", "rpca_solve_many", "rpca_solve_ex", "rpca_footprint_bytes",
            "rpca_strerror", "rpca_version", "rpca_last_error", "rpca_profile_enable", "rpca_profile_read",
-           "rpca_tune_set", "rpca_tune_get", "RPCA_KNOB_EIG_THREADS", "Server",
+           "rpca_tune_set", "rpca_tune_get", "RPCA_KNOB_EIG_THREADS", "RPCA_KNOB_STREAM_KERNEL", "Server",
            "RPCA_OK", "RPCA_NOT_CONVERGED", "RPCA_ERR_ARG", "RPCA_ERR_NOMEM",
            "RPCA_ERR_DEVICE", "RPCA_ERR_NONFINITE", "RPCA_ERR_UNSUPPORTED", "RPCA_F32",
            "RPCA_F64", "RPCA_GRAM_DEFAULT", "RPCA_GRAM_BF16X3", "RPCA_N_MAX"]

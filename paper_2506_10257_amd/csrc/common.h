@@ -13,7 +13,10 @@ namespace rpca {
 constexpr int kThreads = 256;      // threads per streaming workgroup
 constexpr int kTile = 256;         // pixel rows per tile: one row per thread
 constexpr int kGroup = 32;         // partial slots per first-level reduction group
-constexpr int kEigMaxN = 64;       // frame count handled by the LDS eigensolver
+constexpr int kEigMaxN = 64;       // frame count handled by the double-buffered eigensolver
+constexpr int kEigWideMaxN = 112;  // frame count handled by the in-place eigensolver
+constexpr int kEigWideThreads = 1024;
+constexpr int kWideRows = 64;      // pixel rows per tile of the MFMA streaming kernel
 constexpr int kScalars = 4;        // scalar slots at the head of each partial
 
 // Status codes (mirrors include/rpca.h).

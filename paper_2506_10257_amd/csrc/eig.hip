@@ -34,141 +34,13 @@
 #include <type_traits>
 
 #include "common.h"
+#include "eig_common.h"
 #include "launch.h"
 
 namespace rpca {
 namespace {
 
-constexpr double kTiny2 = 1.0e-300;
-constexpr int kMaxSweeps = 40;
-
-template <typename T>
-struct RotEps;
-template <>
-struct RotEps<double> {
-  static constexpr double eps2 = 1.0e-30;
-};
-template <>
-struct RotEps<float> {
-  static constexpr double eps2 = 1.0e-22;
-};
-
-template <typename T>
-__device__ inline bool off_diag_large(double gij, double gii, double gjj) {
-  const double a2 = gij * gij;
-  return a2 > kTiny2 && a2 > RotEps<T>::eps2 * fabs(gii * gjj);
-}
-
-// Round-robin pairing of round r (0 <= r < N2-1) over N2 (even) indices:
-// pair 0 is (N2-1, r), pair k >= 1 is ((r+k) mod M, (r-k) mod M), M = N2-1.
-__device__ inline void pair_indices(int r, int k, int N2, int& p, int& q) {
-  const int M = N2 - 1;
-  int a, b;
-  if (k == 0) {
-    a = N2 - 1;
-    b = r;
-  } else {
-    a = r + k;
-    if (a >= M) a -= M;
-    b = r - k;
-    if (b < 0) b += M;
-  }
-  p = a < b ? a : b;
-  q = a < b ? b : a;
-}
-
-// Per-round column table of J, written by the threads that compute the
-// round's rotations: for index i, column i of J is a_i e_u + b_i e_v with
-// (u, v) the pair containing i, packed as u | v << 8 | rotated << 16, and
-// dg_i the exact shift of the diagonal entry g_ii (-t g_pq for p, +t g_pq
-// for q).  An index paired with the padding index gets the identity column.
-__device__ inline void set_pair_columns(int p, int q, int n, double c, double s, double dt,
-                                        int* cu, double* ca, double* cb, double* cd) {
-  if (q >= n) {
-    cu[p] = p | (p << 8);
-    ca[p] = 1.0;
-    cb[p] = 0.0;
-    cd[p] = 0.0;
-    return;
-  }
-  const int packed = p | (q << 8) | (s != 0.0 ? (1 << 16) : 0);
-  cu[p] = packed;
-  ca[p] = c;
-  cb[p] = -s;
-  cd[p] = -dt;
-  cu[q] = packed;
-  ca[q] = s;
-  cb[q] = c;
-  cd[q] = dt;
-}
-
-// Entry (i, j) of J^T G J from the column table (G with leading dimension LD).
-template <int LD>
-__device__ inline double rotated_entry(int i, int j, const double* G, const int* cu,
-                                       const double* ca, const double* cb, const double* cd) {
-  const int pi = cu[i], pj = cu[j];
-  const int ui = pi & 0xff, vi = (pi >> 8) & 0xff;
-  const int uj = pj & 0xff, vj = (pj >> 8) & 0xff;
-  const double ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
-  double gen = ai * aj * G[ui * LD + uj];
-  gen = fma(ai * bj, G[ui * LD + vj], gen);
-  gen = fma(bi * aj, G[vi * LD + uj], gen);
-  gen = fma(bi * bj, G[vi * LD + vj], gen);
-  const double diag = G[i * LD + i] + cd[i];
-  const bool same_rotated_pair = (pi >> 16) != 0 && (pi & 0xffff) == (pj & 0xffff);
-  return i == j ? diag : (same_rotated_pair ? 0.0 : gen);
-}
-
-// 1/x and 1/sqrt(x) for positive normal x: the hardware estimate refined by
-// two Newton steps (each doubles the number of correct bits).
-__device__ inline double rcp_pos(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = r * fma(-x, r, 2.0);
-  r = r * fma(-x, r, 2.0);
-  return r;
-}
-__device__ inline double rsqrt_pos(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
-}
-
-// Rotation of one pair from the entries of G.
-template <typename T>
-__device__ inline void make_rotation(double gpp, double gqq, double gpq, double& c, double& s,
-                                     double& dt) {
-  if (off_diag_large<T>(gpq, gpp, gqq)) {
-    const double d = gqq - gpp;
-    const double h2 = fma(d, d, 4.0 * gpq * gpq);   // > 0 since gpq != 0
-    const double h = h2 * rsqrt_pos(h2);
-    double t = 2.0 * gpq * rcp_pos(fabs(d) + h);
-    if (d < 0.0) t = -t;
-    c = rsqrt_pos(fma(t, t, 1.0));
-    s = t * c;
-    dt = t * gpq;
-  } else {
-    c = 1.0;
-    s = 0.0;
-    dt = 0.0;
-  }
-}
-
-// Dot product over the zero-padded length NMAX with four independent
-// partial sums (fixed trip count, so every load can be in flight at once).
-template <int NMAX, typename F>
-__device__ inline double dot4(F&& term) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll 4
-  for (int k = 0; k < NMAX; k += 4) {
-    s0 = term(k + 0, s0);
-    s1 = term(k + 1, s1);
-    s2 = term(k + 2, s2);
-    s3 = term(k + 3, s3);
-  }
-  return (s0 + s1) + (s2 + s3);
-}
+using namespace eigk;
 
 template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT)
@@ -291,49 +163,7 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
 
   // 1. Control.
   if (tid == 0) {
-    int go = 0;
-    if (kd == 0) {
-      st->nX1 = scal[1];
-      st->nXF2 = scal[2];
-      st->nonfinite = scal[3] > 0.0 ? 1 : 0;
-      if (st->nonfinite) {
-        st->status = kErrNonfinite;
-        st->done = 1;
-      } else if (st->nX1 == 0.0) {
-        st->status = kOk;
-        st->resid = 0.0;
-        st->done = 1;
-      } else {
-        const double mu = d.mu_in > 0.0
-                              ? d.mu_in
-                              : static_cast<double>(d.m) * static_cast<double>(d.n) / (4.0 * st->nX1);
-        const double lam = d.lam_in > 0.0
-                               ? d.lam_in
-                               : 1.0 / sqrt(static_cast<double>(d.m > d.n ? d.m : d.n));
-        st->mu = mu;
-        st->imu = 1.0 / mu;
-        st->tau = 1.0 / mu;
-        st->lam = lam;
-        st->gamma = lam / mu;
-        go = 1;
-      }
-    } else {
-      st->r2 = scal[0];
-      const double rel = sqrt(st->r2) / sqrt(st->nXF2);
-      st->resid = rel;
-      if (!__builtin_isfinite(st->r2)) {
-        st->status = kErrNonfinite;
-        st->done = 1;
-      } else if (d.tol > 0.0 && rel < d.tol) {
-        st->status = kOk;
-        st->done = 1;
-      } else if (kd >= d.maxit) {
-        st->status = kNotConverged;
-        st->done = 1;
-      } else {
-        go = 1;
-      }
-    }
+    const int go = eigk::control_step(d, st, scal, kd);
     s_go = go;
   }
   __syncthreads();
@@ -493,7 +323,9 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
 
 }  // namespace
 
-int eig_class(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= kEigMaxN ? 64 : 0)); }
+int eig_class(int n) {
+  return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= kEigMaxN ? 64 : (n <= kEigWideMaxN ? kEigWideMaxN : 0)));
+}
 
 namespace {
 // Threads per eigensolve workgroup, per [dtype][class 16/32/64].  Defaults

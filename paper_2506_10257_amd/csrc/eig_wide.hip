@@ -1,0 +1,252 @@
+// FP64 eigensolve and singular value thresholding weights for windows of 65
+// to 112 frames (paper Sec. II-A, Eq. 4; the paper's own reference uses up to
+// 132 frames, Sec. III-D).
+//
+// Same method as the LDS eigensolver of the smaller classes: cyclic
+// two-sided Jacobi on the n x n Gram G = A^T A with the round-robin parallel
+// ordering, rotations of the smaller angle, and P = V diag(w) V^T with
+// w_i = max(sigma_i - tau, 0) / sigma_i.  At these sizes two copies of G and
+// V do not fit in the 160 KB of LDS, so the rotations are applied in place:
+//
+//   * G is kept as its packed upper triangle.  In one round the disjoint
+//     pairs (p_k, q_k) split G into 2 x 2 blocks, and block (k1, k2) of
+//     J^T G J depends only on block (k1, k2) of G, so each thread owns whole
+//     blocks and overwrites them;
+//   * V is kept in full; row i of V J depends only on row i, so each thread
+//     owns (row, pair) items and overwrites V[i][p], V[i][q];
+//   * a round is [apply the round's rotations] barrier [the first wave
+//     computes the next round's rotations from the updated G] barrier.
+//
+// Every solve step starts from V = I (no warm start), so V is orthogonal to
+// the rounding of the rotations of one step.
+#include "common.h"
+#include "eig_common.h"
+#include "launch.h"
+
+namespace rpca {
+namespace {
+
+using namespace eigk;
+
+__device__ inline int pk(int i, int j) {  // packed upper index, i <= j
+  return j * (j + 1) / 2 + i;
+}
+__device__ inline int pks(int i, int j) { return i <= j ? pk(i, j) : pk(j, i); }
+
+template <typename T, int NMAX, int NT>
+__global__ void __launch_bounds__(NT)
+k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
+  constexpr int NPK = NMAX * (NMAX + 1) / 2;
+  constexpr int LDV = NMAX + 1;
+  constexpr int NPM = NMAX / 2;                               // pairs per round at most
+  constexpr int NBLK = NPM * (NPM + 1) / 2;                   // 2x2 blocks (k1 <= k2)
+  constexpr int MB = (NBLK + NT - 1) / NT;                    // blocks per thread
+  constexpr int MV = (NMAX * NPM + NT - 1) / NT;              // V items per thread
+  static_assert(NMAX % 2 == 0, "even class size");
+  __shared__ double Gp[NPK];
+  __shared__ double Vs[NMAX * LDV];
+  __shared__ int tp[NPM], tq[NPM];
+  __shared__ double tc[NPM], ts[NPM], tdt[NPM];
+  __shared__ double w[NMAX];
+  __shared__ double scal[kScalars];
+  __shared__ int s_go;
+
+  const int tid = threadIdx.x;
+  const SolveDesc& d = descs[ids[blockIdx.x]];
+  SolveState* st = d.st;
+  if (st->done) return;
+  const int n = d.n;
+  const int nb = d.nb;
+  const int kd = st->iter;
+
+  for (int idx = tid; idx < NPK; idx += NT) Gp[idx] = 0.0;
+  for (int idx = tid; idx < NMAX * LDV; idx += NT) {
+    const int i = idx / LDV, j = idx - (idx / LDV) * LDV;
+    Vs[idx] = (i == j && i < n) ? 1.0 : 0.0;
+  }
+  if (tid < NMAX) w[tid] = 0.0;
+  __syncthreads();
+
+  // 0. Sum the group partials of the streaming pass in group order; the Gram
+  // goes into the packed upper triangle.
+  {
+    const int nblk = gram_blocks((n + 3) >> 2);
+    const int nent = kScalars + nblk * 16;
+    constexpr int kChunk = 16;
+    for (int idx = tid; idx < nent; idx += NT) {
+      double sum = 0.0;
+      for (int q0 = 0; q0 < d.groups; q0 += kChunk) {
+        const int c = min(kChunk, d.groups - q0);
+        double v[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q)
+          v[q] = q < c ? d.gpartials[static_cast<size_t>(q0 + q) * d.pstride + idx] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q)
+          if (q < c) sum += v[q];
+      }
+      if (idx < kScalars) {
+        scal[idx] = sum;
+      } else {
+        const int g = idx - kScalars;
+        const int blk = g >> 4, e = g & 15;
+        int bj = 0;
+        while ((bj + 1) * (bj + 2) / 2 <= blk) ++bj;
+        const int bi = blk - bj * (bj + 1) / 2;
+        const int i = 4 * bi + (e >> 2), j = 4 * bj + (e & 3);
+        if (i <= j && j < n) Gp[pk(i, j)] = sum;
+      }
+    }
+  }
+  __syncthreads();
+
+  if (tid == 0) s_go = control_step(d, st, scal, kd);
+  __syncthreads();
+  if (!s_go) return;
+  const double tau = st->tau;
+
+  const int N2 = n + (n & 1);
+  const int M = N2 - 1;
+  const int NP = N2 / 2;
+  const int nblk2 = NP * (NP + 1) / 2;
+
+  // Owned 2x2 blocks (pair indices k1 <= k2) and V items (row, pair).
+  int bk1[MB], bk2[MB], vi[MV], vk[MV];
+#pragma unroll
+  for (int q = 0; q < MB; ++q) {
+    const int b = tid + q * NT;
+    int k2 = 0;
+    if (b < nblk2) {
+      while ((k2 + 1) * (k2 + 2) / 2 <= b) ++k2;
+    }
+    bk2[q] = k2;
+    bk1[q] = b < nblk2 ? b - k2 * (k2 + 1) / 2 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < MV; ++q) {
+    const int it = tid + q * NT;
+    vk[q] = NP > 0 ? it % NP : 0;
+    vi[q] = NP > 0 ? it / NP : n;
+  }
+
+  // Rotations of round r for pairs handled by the first wave.
+  auto make_round = [&](int r) {
+    if (tid < NP) {
+      int p, q;
+      pair_indices(r, tid, N2, p, q);
+      double c = 1.0, s = 0.0, dt = 0.0;
+      if (q < n) make_rotation<T>(Gp[pk(p, p)], Gp[pk(q, q)], Gp[pk(p, q)], c, s, dt);
+      tp[tid] = p;
+      tq[tid] = q;
+      tc[tid] = c;
+      ts[tid] = s;
+      tdt[tid] = dt;
+    }
+  };
+
+  int sweeps = 0;
+  for (; sweeps < kMaxSweeps && n > 1; ++sweeps) {
+    int need = 0;
+    for (int idx = tid; idx < n * (n + 1) / 2; idx += NT) {
+      int j = 0;
+      while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+      const int i = idx - j * (j + 1) / 2;
+      if (i < j && off_diag_large<T>(Gp[idx], Gp[pk(i, i)], Gp[pk(j, j)])) need = 1;
+    }
+    make_round(0);
+    if (!__syncthreads_or(need)) break;
+    for (int r = 0; r < M; ++r) {
+      // apply round r: G blocks and V items, in place
+#pragma unroll
+      for (int q = 0; q < MB; ++q) {
+        if (tid + q * NT < nblk2) {
+          const int k1 = bk1[q], k2 = bk2[q];
+          const int p1 = tp[k1], q1 = tq[k1], p2 = tp[k2], q2 = tq[k2];
+          const double c1 = tc[k1], s1 = ts[k1], c2 = tc[k2], s2 = ts[k2];
+          if (k1 == k2) {
+            if (s1 != 0.0) {
+              const double dt = tdt[k1];
+              Gp[pk(p1, p1)] -= dt;
+              Gp[pk(q1, q1)] += dt;
+              Gp[pk(p1, q1)] = 0.0;
+            }
+          } else if (s1 != 0.0 || s2 != 0.0) {
+            const int ia = pks(p1, p2), ib = pks(p1, q2), ic = pks(q1, p2), id = pks(q1, q2);
+            const double b_pp = Gp[ia], b_pq = Gp[ib], b_qp = Gp[ic], b_qq = Gp[id];
+            // T = B J2 (columns p2, q2), then J1^T T (rows p1, q1)
+            const double t_pp = fma(c2, b_pp, -s2 * b_pq), t_pq = fma(s2, b_pp, c2 * b_pq);
+            const double t_qp = fma(c2, b_qp, -s2 * b_qq), t_qq = fma(s2, b_qp, c2 * b_qq);
+            Gp[ia] = fma(c1, t_pp, -s1 * t_qp);
+            Gp[ib] = fma(c1, t_pq, -s1 * t_qq);
+            Gp[ic] = fma(s1, t_pp, c1 * t_qp);
+            Gp[id] = fma(s1, t_pq, c1 * t_qq);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < MV; ++q) {
+        const int i = vi[q];
+        if (i < n) {
+          const int k = vk[q];
+          const double s = ts[k];
+          if (s != 0.0) {
+            const double c = tc[k];
+            double* row = Vs + i * LDV;
+            const int p = tp[k], qq = tq[k];
+            const double vp = row[p], vq = row[qq];
+            row[p] = fma(c, vp, -s * vq);
+            row[qq] = fma(s, vp, c * vq);
+          }
+        }
+      }
+      __syncthreads();
+      if (r + 1 < M) make_round(r + 1);
+      __syncthreads();
+    }
+  }
+
+  // SVT weights and P = V diag(w) V^T (exactly symmetric), in storage precision.
+  if (tid < n) {
+    const double sg = sqrt(fmax(Gp[pk(tid, tid)], 0.0));
+    w[tid] = sg > tau ? (sg - tau) / sg : 0.0;
+  }
+  __syncthreads();
+  const gptr<T> Pd = as_global<T>(d.P);
+  const int nbup = nb * (nb + 1) / 2;
+  for (int idx = tid; idx < nbup; idx += NT) {
+    int j = 0;
+    while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+    const int i = idx - j * (j + 1) / 2;
+    double s = 0.0;
+    if (j < n) {
+      const double* vi_ = Vs + i * LDV;
+      const double* vj_ = Vs + j * LDV;
+      s = dot4<NMAX>([&](int k, double acc) { return fma(vi_[k] * w[k], vj_[k], acc); });
+    }
+    Pd[i * nb + j] = static_cast<T>(s);
+    Pd[j * nb + i] = static_cast<T>(s);
+  }
+  if (tid == 0) {
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += w[k] != 0.0 ? 1 : 0;
+    st->rank = rank;
+    st->sweeps = sweeps;
+    st->sweeps_total += sweeps;
+    st->iter = kd + 1;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_eig_wide(int dtype, int grid, hipStream_t stream, const SolveDesc* descs,
+                           const int32_t* ids) {
+  if (grid <= 0) return hipSuccess;
+  const dim3 g(grid), b(kEigWideThreads);
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_eig_wide<double, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+  else
+    hipLaunchKernelGGL((k_eig_wide<float, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+  return hipGetLastError();
+}
+
+}  // namespace rpca

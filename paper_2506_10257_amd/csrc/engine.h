@@ -26,15 +26,20 @@ namespace rpca {
 
 struct Geo {
   int nb = 0, tiles = 0, tps = 1, slots = 0, groups = 0, pstride = 0;
+  int kind = 0;  // streaming kernel: 0 register (thread per row), 1 MFMA tiles
+  int prec = 0;  // contraction precision: 0 storage/FP64, 1 split-BF16
   size_t es = 0;
 };
+
+// Launch-class key of a solve: frame class, kernel kind, precision.
+inline int class_key(const Geo& g) { return g.nb | (g.kind << 8) | (g.prec << 9); }
 
 // Byte offsets of one solve's device memory.
 struct Big {
   size_t S0, S1, Y0, Y1, part, gpart, P, V, state, trace, total;
 };
 
-bool geometry(int64_t m, int64_t n, int dtype, Geo& g);
+bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g);
 Big big_layout(int64_t m, int64_t n, const Geo& g);
 
 struct SolveRec {
@@ -104,7 +109,7 @@ hipError_t enqueue_snapshot(const Plan& plan, Lanes& L, int slot);
 
 // Validate one problem and fill its record (parameters, geometry, layout).
 // Returns RPCA_OK, RPCA_ERR_ARG or RPCA_ERR_UNSUPPORTED.
-int make_rec(const rpca_problem& p, int dtype, SolveRec& r);
+int make_rec(const rpca_problem& p, int dtype, int gram_mode, SolveRec& r);
 // Spread solves over lanes, balancing m*n, largest first (stable).
 void assign_lanes(std::vector<SolveRec*>& recs, int nlanes);
 // Memory pool of the device: keep freed blocks cached (set once per device).
@@ -116,5 +121,8 @@ void set_error(const char* what, hipError_t e);
 void set_error_text(const char* text);
 
 int nb_class(int64_t n, int dtype);
+// FP32 register classes: streaming kernel choice (0 register, 1 MFMA tiles).
+int stream_kernel_choice(int cls);
+bool set_stream_kernel_choice(int cls, int v);
 
 }  // namespace rpca

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -117,8 +118,11 @@ bool overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
-hipError_t launch_stream(int dtype, int nb, int mode, int grid, hipStream_t s, const SolveDesc* d,
+// `key` is a class key (class_key): frame class, kernel kind and precision.
+hipError_t launch_stream(int dtype, int key, int mode, int grid, hipStream_t s, const SolveDesc* d,
                          const WorkItem* it) {
+  const int nb = key & 0xff, kind = (key >> 8) & 1, prec = (key >> 9) & 1;
+  if (kind == 1) return launch_wide(nb, mode, prec, grid, s, d, it);
   return dtype == RPCA_F32 ? launch_stream_f32(nb, mode, grid, s, d, it)
                            : launch_stream_f64(nb, mode, grid, s, d, it);
 }
@@ -165,6 +169,13 @@ void set_error(const char* what, hipError_t e) {
 void set_error_text(const char* text) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", text); }
 
 // ---------------------------------------------------------------- geometry
+namespace {
+// Streaming kernel per FP32 register frame class (index: class value 0..64):
+// 0 = register kernel, 1 = MFMA tile kernel.  Classes above 64 frames and the
+// split-BF16 mode always use the MFMA tile kernel.
+std::atomic<int> g_stream_kernel[kEigMaxN + 1];
+}  // namespace
+
 int nb_class(int64_t n, int dtype) {
   if (dtype == RPCA_F32) {
     for (int c : kClassesF32)
@@ -176,18 +187,46 @@ int nb_class(int64_t n, int dtype) {
   return 0;
 }
 
-bool geometry(int64_t m, int64_t n, int dtype, Geo& g) {
+int stream_kernel_choice(int cls) {
+  if (cls < 0 || cls > kEigMaxN) return -1;
+  for (int c : kClassesF32)
+    if (c == cls) return g_stream_kernel[cls].load(std::memory_order_relaxed);
+  return -1;
+}
+
+bool set_stream_kernel_choice(int cls, int v) {
+  if (stream_kernel_choice(cls) < 0 || (v != 0 && v != 1)) return false;
+  g_stream_kernel[cls].store(v, std::memory_order_relaxed);
+  return true;
+}
+
+bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g) {
   if (m < 1 || n < 1 || n > RPCA_N_MAX) return false;
-  g.nb = nb_class(n, dtype);
-  if (g.nb == 0 || n > kEigMaxN) return false;
   if (m >= (int64_t(1) << 30)) return false;  // row offsets are 32-bit byte offsets
-  const int64_t tiles = (m + kTile - 1) / kTile;
-  g.tiles = static_cast<int>(tiles);
-  g.tps = 1;  // one tile per work item (and per partial slot)
-  g.slots = g.tiles;
+  g.es = dtype == RPCA_F32 ? 4 : 8;
+  g.prec = gram_mode == RPCA_GRAM_BF16X3 ? 1 : 0;
+  if (g.prec && dtype != RPCA_F32) return false;
+  const int reg = nb_class(n, dtype);
+  g.kind = 1;
+  if (!g.prec && reg != 0 && (dtype == RPCA_F64 || stream_kernel_choice(reg) == 0)) g.kind = 0;
+  if (g.kind == 0) {
+    g.nb = reg;
+    const int64_t tiles = (m + kTile - 1) / kTile;
+    g.tiles = static_cast<int>(tiles);
+    g.tps = 1;  // one tile per work item (and per partial slot)
+  } else {
+    if (dtype != RPCA_F32 || n > kEigWideMaxN) return false;
+    g.nb = static_cast<int>((n + 15) / 16 * 16);
+    const int64_t tiles = (m + kWideRows - 1) / kWideRows;
+    g.tiles = static_cast<int>(tiles);
+    // rows per workgroup: at least 16 per frame, so the O(nb^2) Gram partial
+    // stays a few percent of the workgroup's streamed bytes
+    const int rows = std::max(1024, 16 * g.nb);
+    g.tps = (rows + kWideRows - 1) / kWideRows;
+  }
+  g.slots = (g.tiles + g.tps - 1) / g.tps;
   g.groups = (g.slots + kGroup - 1) / kGroup;
   g.pstride = pstride_for(g.nb);
-  g.es = dtype == RPCA_F32 ? 4 : 8;
   return true;
 }
 
@@ -225,17 +264,18 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
   std::vector<GroupItem> gitems;
   std::vector<int32_t> ids;
   for (LaneRun& lr : plan.lanes) {
-    std::vector<int> nbs;
+    std::vector<int> keys;
     for (int i : lr.solves)
-      if (std::find(nbs.begin(), nbs.end(), recs[i]->geo.nb) == nbs.end()) nbs.push_back(recs[i]->geo.nb);
-    for (int nb : nbs) {
+      if (std::find(keys.begin(), keys.end(), class_key(recs[i]->geo)) == keys.end())
+        keys.push_back(class_key(recs[i]->geo));
+    for (int key : keys) {
       const int off = static_cast<int>(items.size());
       for (int i : lr.solves)
-        if (recs[i]->geo.nb == nb)
+        if (class_key(recs[i]->geo) == key)
           for (int q = 0; q < recs[i]->geo.slots; ++q) items.push_back(WorkItem{i, q});
-      lr.classes.push_back({nb, {off, static_cast<int>(items.size()) - off}});
+      lr.classes.push_back({key, {off, static_cast<int>(items.size()) - off}});
     }
-    for (int cls : {16, 32, 64}) {
+    for (int cls : {16, 32, 64, kEigWideMaxN}) {
       const int off = static_cast<int>(ids.size());
       for (int i : lr.solves)
         if (eig_class(recs[i]->n) == cls) ids.push_back(i);
@@ -424,8 +464,12 @@ static hipError_t enqueue_iterations_at(const Plan& plan, const Lanes& L, int it
     for (int k = 0; k < iters; ++k) {
       for (const auto& er : lr.eigs) {
         ev_begin(s, 1, first_iter + k, static_cast<int>(l), -1);
-        EQ(launch_eig(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s, plan.descs,
-                      plan.ids + er.second.first));
+        if (er.first == kEigWideMaxN)
+          EQ(launch_eig_wide(plan.dtype == RPCA_F32 ? 1 : 0, er.second.second, s, plan.descs,
+                             plan.ids + er.second.first));
+        else
+          EQ(launch_eig(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s, plan.descs,
+                        plan.ids + er.second.first));
         ev_end(s);
       }
       for (size_t c = 0; c < lr.classes.size(); ++c) {
@@ -477,14 +521,14 @@ hipError_t enqueue_snapshot(const Plan& plan, Lanes& L, int slot) {
 
 #undef EQ
 
-int make_rec(const rpca_problem& p, int dtype, SolveRec& r) {
+int make_rec(const rpca_problem& p, int dtype, int gram_mode, SolveRec& r) {
   if (!p.M || !p.L || !p.S || p.m < 1 || p.n < 1 || p.n > RPCA_N_MAX || p.maxit < 1)
     return RPCA_ERR_ARG;
   if (!std::isfinite(p.lambda) || !std::isfinite(p.mu) || std::isnan(p.tol)) return RPCA_ERR_ARG;
   const size_t bytes = static_cast<size_t>(p.m) * static_cast<size_t>(p.n) * (dtype == RPCA_F32 ? 4 : 8);
   if (overlap(p.M, p.L, bytes) || overlap(p.M, p.S, bytes) || overlap(p.L, p.S, bytes))
     return RPCA_ERR_ARG;
-  if (!geometry(p.m, p.n, dtype, r.geo)) return RPCA_ERR_UNSUPPORTED;
+  if (!geometry(p.m, p.n, dtype, gram_mode, r.geo)) return RPCA_ERR_UNSUPPORTED;
   r.big = big_layout(p.m, p.n, r.geo);
   r.M = p.M;
   r.L = p.L;
@@ -530,11 +574,11 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   if (count < 1 || probs == nullptr) return RPCA_ERR_ARG;
   if (dtype != RPCA_F32 && dtype != RPCA_F64) return RPCA_ERR_ARG;
   if (gram_mode != RPCA_GRAM_DEFAULT && gram_mode != RPCA_GRAM_BF16X3) return RPCA_ERR_ARG;
-  if (gram_mode == RPCA_GRAM_BF16X3) return RPCA_ERR_UNSUPPORTED;
+  if (gram_mode == RPCA_GRAM_BF16X3 && dtype != RPCA_F32) return RPCA_ERR_ARG;
 
   std::vector<SolveRec> recs(count);
   for (int i = 0; i < count; ++i) {
-    const int vrc = make_rec(probs[i], dtype, recs[i]);
+    const int vrc = make_rec(probs[i], dtype, gram_mode, recs[i]);
     if (vrc != RPCA_OK) return vrc;
   }
 
@@ -707,10 +751,10 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
         }
       } else {
         const LaneRun& lr = plan.lanes[e.lane];
-        const int nb = lr.classes[e.cls].first;
+        const int key = lr.classes[e.cls].first;
         double bytes = 0;
         for (int i : lr.solves) {
-          if (recs[i].geo.nb == nb && recs[i].st.iter >= e.iter) {
+          if (class_key(recs[i].geo) == key && recs[i].st.iter >= e.iter) {
             const double words = e.iter == 1 ? 3.0 : 5.0;
             bytes += words * static_cast<double>(recs[i].m) * recs[i].n * recs[i].geo.es;
           }
@@ -809,7 +853,7 @@ int rpca_solve_f32(const float* M, int64_t m, int64_t n, double lambda, double m
 size_t rpca_footprint_bytes(int64_t m, int64_t n, int32_t dtype) {
   if (dtype != RPCA_F32 && dtype != RPCA_F64) return 0;
   Geo g;
-  if (!geometry(m, n, dtype, g)) return 0;
+  if (!geometry(m, n, dtype, RPCA_GRAM_DEFAULT, g)) return 0;
   const Big b = big_layout(m, n, g);
   // plus this solve's share of a control block
   return b.total + al256(sizeof(SolveDesc) + sizeof(SolveState) + sizeof(int32_t)) +
@@ -834,6 +878,10 @@ const char* rpca_version(void) { return "rpca_mi355x 0.3"; }
 int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value) {
   if (dtype != RPCA_F32 && dtype != RPCA_F64) return RPCA_ERR_ARG;
   if (knob == RPCA_KNOB_EIG_THREADS) return set_eig_threads(dtype, cls, value) ? RPCA_OK : RPCA_ERR_ARG;
+  if (knob == RPCA_KNOB_STREAM_KERNEL) {
+    if (dtype != RPCA_F32) return RPCA_ERR_ARG;
+    return set_stream_kernel_choice(cls, value) ? RPCA_OK : RPCA_ERR_ARG;
+  }
   return RPCA_ERR_ARG;
 }
 
@@ -842,6 +890,11 @@ int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls) {
   if (knob == RPCA_KNOB_EIG_THREADS) {
     const int v = eig_threads(dtype, cls);
     return v > 0 ? v : RPCA_ERR_ARG;
+  }
+  if (knob == RPCA_KNOB_STREAM_KERNEL) {
+    if (dtype != RPCA_F32) return RPCA_ERR_ARG;
+    const int v = stream_kernel_choice(cls);
+    return v >= 0 ? v : RPCA_ERR_ARG;
   }
   return RPCA_ERR_ARG;
 }

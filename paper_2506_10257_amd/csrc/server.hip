@@ -286,7 +286,8 @@ size_t rpca_server_request_bytes(int64_t m, int64_t n, int32_t dtype) {
 rpca_server* rpca_server_create(int32_t dtype, int32_t gram_mode, size_t hbm_budget,
                                 int32_t max_active, int32_t quantum, int32_t flags, void* stream) {
   if (dtype != RPCA_F32 && dtype != RPCA_F64) return nullptr;
-  if (gram_mode != RPCA_GRAM_DEFAULT) return nullptr;
+  if (gram_mode != RPCA_GRAM_DEFAULT && gram_mode != RPCA_GRAM_BF16X3) return nullptr;
+  if (gram_mode == RPCA_GRAM_BF16X3 && dtype != RPCA_F32) return nullptr;
   if (hbm_budget == 0 || max_active < 1 || quantum < 1) return nullptr;
   if (flags & ~RPCA_SERVER_SIMULATE) return nullptr;
   rpca_server* s = new (std::nothrow) rpca_server();
@@ -315,7 +316,7 @@ int rpca_server_submit(rpca_server* s, const rpca_problem* p, int64_t tag) {
   if (!r) return RPCA_ERR_NOMEM;
   r->p = *p;
   r->tag = tag;
-  const int rc = make_rec(r->p, s->dtype, r->rec);
+  const int rc = make_rec(r->p, s->dtype, s->gram_mode, r->rec);
   if (rc != RPCA_OK) {
     delete r;
     return rc;

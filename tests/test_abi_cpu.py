@@ -108,3 +108,33 @@ def test_tuning_knobs(lib):
     assert rp.rpca_tune_set(99, rp.RPCA_F32, 32, 256) == rp.RPCA_ERR_ARG
     assert rp.rpca_tune_get(99, rp.RPCA_F32, 32) == rp.RPCA_ERR_ARG
     assert rp.rpca_tune_get(K, rp.RPCA_F32, 64) == old
+
+
+def test_frame_limits(lib):
+    A, B, C = 1 << 40, 2 << 40, 3 << 40
+    assert _lib.RPCA_N_MAX == 112
+    assert _call(lib, A, 100, 113, B, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 33, B, C, fn="rpca_solve_f64")[0] == _lib.RPCA_ERR_UNSUPPORTED
+    assert lib.rpca_footprint_bytes(4096, 112, _lib.RPCA_F32) > 0
+    assert lib.rpca_footprint_bytes(4096, 113, _lib.RPCA_F32) == 0
+    assert lib.rpca_footprint_bytes(4096, 33, _lib.RPCA_F64) == 0
+    # the split-BF16 mode is FP32 only
+    p = _lib.RpcaProblem()
+    p.M, p.L, p.S, p.m, p.n, p.maxit = A, B, C, 100, 4, 10
+    assert lib.rpca_solve_ex(ctypes.byref(p), _lib.RPCA_F64, _lib.RPCA_GRAM_BF16X3, None) == _lib.RPCA_ERR_ARG
+
+
+def test_stream_kernel_knob(lib):
+    import paper_2506_10257_amd as rp
+    K = rp.RPCA_KNOB_STREAM_KERNEL
+    for cls in (4, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 56, 60, 64):
+        assert rp.rpca_tune_get(K, rp.RPCA_F32, cls) in (0, 1)
+    old = rp.rpca_tune_get(K, rp.RPCA_F32, 40)
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 40, 1) == rp.RPCA_OK
+    assert rp.rpca_tune_get(K, rp.RPCA_F32, 40) == 1
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 40, old) == rp.RPCA_OK
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 44, 1) == rp.RPCA_ERR_ARG   # not a class
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 80, 0) == rp.RPCA_ERR_ARG   # tile kernel only
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 40, 2) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_set(K, rp.RPCA_F64, 20, 1) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_get(K, rp.RPCA_F64, 20) == rp.RPCA_ERR_ARG

@@ -1,0 +1,121 @@
+"""Windows of 65-112 frames (MFMA tile streaming kernel and the in-place
+eigensolver), the tile kernel on the smaller frame classes, and the
+split-BF16 precision variant, against the FP64 oracle.
+
+Bars as for the other FP32 paths: relative Frobenius error <= 1e-4 in L and
+S, iterations within one, Dice >= 0.999 on the bound-bubble mask.  The
+split-BF16 mode carries larger contraction error; its error is measured and
+stated, with a loose bound that catches a broken kernel.
+"""
+import numpy as np
+import pytest
+
+import paper_2506_10257_amd as rp
+from oracle import rpca, rel_fro, dice, bound_threshold
+from synth import batch_window
+from tests.gpu_helpers import device, to_dev, to_host, report
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(X, gram_mode=rp.RPCA_GRAM_DEFAULT, tol=1e-6, maxit=300):
+    M = to_dev(X, np.float32)
+    r = rp.solve(M, tol=tol, maxit=maxit, gram_mode=gram_mode)
+    return to_host(r.L), to_host(r.S), r.iterations, r.status
+
+
+def _check(name, w, ref, L, S, it, bar=1e-4, it_slack=1):
+    theta = bound_threshold(w.L_gt, w.bound_mask)
+    eL, eS = rel_fro(L, ref.L), rel_fro(S, ref.S)
+    d = dice(L >= theta, ref.L >= theta)
+    report(name, it=it, it_ref=ref.iterations, relL=eL, relS=eS, dice=d)
+    assert abs(it - ref.iterations) <= it_slack
+    assert eL <= bar and eS <= bar
+    assert d >= 0.999
+    return eL, eS, d
+
+
+# (H, W, n): ragged row counts (not a multiple of the 64-row tile), odd and
+# even frame counts, every wide class (80, 96, 112) and its edges.
+WIDE = [(48, 48, 65), (50, 47, 80), (40, 60, 81), (48, 49, 99), (44, 50, 100), (40, 52, 112)]
+
+
+@pytest.mark.parametrize("H,W,n", WIDE)
+def test_wide_fp32_matches_oracle(H, W, n):
+    device()
+    w = batch_window(H, W, n, 7000 + n)
+    X = w.X()
+    ref = rpca(X, tol=1e-6, maxit=300)
+    L, S, it, rc = _solve(X)
+    _check(f"wide {H}x{W}x{n}", w, ref, L, S, it)
+
+
+@pytest.mark.parametrize("k", [1, 2, 7])
+def test_wide_iterate_parity(k):
+    """Fixed iteration counts (tol = 0): the k-th iterate against the oracle's."""
+    device()
+    w = batch_window(40, 40, 100, 7101)
+    X = w.X()
+    ref = rpca(X, tol=0.0, maxit=k)
+    L, S, it, rc = _solve(X, tol=0.0, maxit=k)
+    assert it == k and rc == rp.RPCA_NOT_CONVERGED
+    eL, eS = rel_fro(L, ref.L), rel_fro(S, ref.S)
+    report(f"wide iterate k={k}", relL=eL, relS=eS)
+    assert eL <= 1e-5 and eS <= 1e-5
+
+
+@pytest.mark.parametrize("n", [10, 20, 40, 64])
+def test_tile_kernel_on_register_classes(n):
+    """The MFMA tile kernel selected for a class the register kernel also serves."""
+    device()
+    K = rp.RPCA_KNOB_STREAM_KERNEL
+    cls = next(c for c in (4, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 56, 60, 64) if c >= n)
+    w = batch_window(64, 72, n, 7200 + n)
+    X = w.X()
+    ref = rpca(X, tol=1e-6, maxit=300)
+    old = rp.rpca_tune_get(K, rp.RPCA_F32, cls)
+    try:
+        assert rp.rpca_tune_set(K, rp.RPCA_F32, cls, 1) == rp.RPCA_OK
+        L, S, it, rc = _solve(X)
+    finally:
+        rp.rpca_tune_set(K, rp.RPCA_F32, cls, old)
+    _check(f"tile kernel n={n}", w, ref, L, S, it)
+
+
+def test_zero_input_wide():
+    import torch
+    device()
+    M = torch.zeros((100, 3000), device="cuda").t()
+    r = rp.solve(M, tol=1e-6, maxit=10)
+    assert r.status == rp.RPCA_OK and r.iterations == 0
+    assert bool((r.L == 0).all()) and bool((r.S == 0).all())
+
+
+def test_wide_batch_bitwise_equals_alone():
+    import torch
+    device()
+    shapes = [(40, 40, 100), (32, 48, 20), (48, 40, 80), (30, 30, 112), (64, 64, 10)]
+    Ms = [to_dev(batch_window(H, W, n, 7300 + i).X(), np.float32) for i, (H, W, n) in enumerate(shapes)]
+    alone = [rp.solve(M, tol=1e-6, maxit=200) for M in Ms]
+    many = rp.solve_many(Ms, tol=1e-6, maxit=200)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, many):
+        assert a.iterations == b.iterations
+        assert torch.equal(a.L, b.L) and torch.equal(a.S, b.S)
+
+
+@pytest.mark.parametrize("H,W,n", [(64, 64, 40), (48, 50, 100)])
+def test_bf16x3_error_stated(H, W, n):
+    """Split-BF16 contractions: the error against the FP64 oracle is measured
+    and reported; the bound only catches a broken kernel."""
+    device()
+    w = batch_window(H, W, n, 7400 + n)
+    X = w.X()
+    ref = rpca(X, tol=1e-6, maxit=300)
+    L, S, it, rc = _solve(X, gram_mode=rp.RPCA_GRAM_BF16X3)
+    theta = bound_threshold(w.L_gt, w.bound_mask)
+    eL, eS = rel_fro(L, ref.L), rel_fro(S, ref.S)
+    d = dice(L >= theta, ref.L >= theta)
+    report(f"bf16x3 {H}x{W}x{n}", it=it, it_ref=ref.iterations, relL=eL, relS=eS, dice=d)
+    assert eL <= 2e-2 and eS <= 2e-2
+    assert d >= 0.99
