@@ -214,8 +214,12 @@ def run_serve(args):
     done_at, iters, status = {}, {}, {}
     t0 = time.perf_counter()
     i = 0
+    next_note = 10.0
     while len(done_at) < len(reqs):
         now = time.perf_counter() - t0
+        if now >= next_note:
+            print(f"[serve] {now:.0f} s: {len(done_at)} of {len(reqs)} done", file=sys.stderr, flush=True)
+            next_note += 10.0
         while i < len(reqs) and reqs[i][0] <= now:
             srv.submit(inputs[i], tag=i, tol=tol, maxit=maxit)
             i += 1
@@ -239,8 +243,12 @@ def run_serve(args):
     p_done = []
     t0 = time.perf_counter()
     p_work = 0
+    next_note = 10.0
     for k, (t, _, _, _) in enumerate(reqs):
         now = time.perf_counter() - t0
+        if now >= next_note:
+            print(f"[plain] {now:.0f} s: {k} of {len(reqs)} done", file=sys.stderr, flush=True)
+            next_note += 10.0
         if now < t:
             time.sleep(t - now)
         r = rp.solve(inputs[k], tol=tol, maxit=maxit)

@@ -52,6 +52,7 @@ struct SolveDesc {
   double* gpartials;      // groups x pstride
   void* P;                // nb x nb thresholding projector, storage precision
   double* V;              // nb x nb eigenvectors of the last eigensolve
+  double* escratch;       // kEigWideMaxN^2 doubles for the wide eigensolver (else null)
   SolveState* st;
   int64_t* wgtrace;       // per-slot timestamps (trace builds only, else null)
   int64_t m;

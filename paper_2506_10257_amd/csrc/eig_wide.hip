@@ -17,8 +17,13 @@
 //   * a round is [apply the round's rotations] barrier [the first wave
 //     computes the next round's rotations from the updated G] barrier.
 //
-// Every solve step starts from V = I (no warm start), so V is orthogonal to
-// the rounding of the rotations of one step.
+// Warm start: from the second step on, the rotations start from the previous
+// step's eigenvectors V, on G~ = V^T G V, which is nearly diagonal once the
+// iteration settles.  The two products run on the f64 matrix cores
+// (W = G V goes through a per-solve global scratch buffer, since LDS holds G
+// and V already).  These classes serve FP32 solves only, so V is not
+// re-orthonormalised: the rounding of the rotations stays far below the
+// FP32 rounding of the data.
 #include "common.h"
 #include "eig_common.h"
 #include "launch.h"
@@ -59,10 +64,13 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   const int nb = d.nb;
   const int kd = st->iter;
 
+  const bool warm = kd > 0;
   for (int idx = tid; idx < NPK; idx += NT) Gp[idx] = 0.0;
   for (int idx = tid; idx < NMAX * LDV; idx += NT) {
     const int i = idx / LDV, j = idx - (idx / LDV) * LDV;
-    Vs[idx] = (i == j && i < n) ? 1.0 : 0.0;
+    double v = (i == j && i < n) ? 1.0 : 0.0;
+    if (warm && i < n && j < n) v = d.V[i * nb + j];
+    Vs[idx] = v;
   }
   if (tid < NMAX) w[tid] = 0.0;
   __syncthreads();
@@ -104,6 +112,67 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   __syncthreads();
   if (!s_go) return;
   const double tau = st->tau;
+
+  if (warm) {
+    // W = G V (every 16 x 16 block) into the scratch buffer, then the upper
+    // blocks of G~ = V^T W, written over G once every wave is past its reads
+    // of G.  The f64 MFMA result of lane l, register r is entry
+    // (l/16 + 4r, l%16) of the 16 x 16 block.
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int NWV = NT / 64;
+    constexpr int NT16 = NMAX / 16;
+    constexpr int NUT = NT16 * (NT16 + 1) / 2;
+    constexpr int MT = (NUT + NWV - 1) / NWV;
+    const int wv = tid >> 6, l = tid & 63;
+    const gptr<double> Wg = as_global<double>(static_cast<void*>(d.escratch));
+    for (int t = wv; t < NT16 * NT16; t += NWV) {
+      const int bi = t / NT16, bj = t - (t / NT16) * NT16;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int kk = 0; kk < NMAX / 4; ++kk) {
+        const int kq = 4 * kk + (l >> 4);
+        const double a = Gp[pks(16 * bi + (l & 15), kq)];
+        const double b = Vs[kq * LDV + 16 * bj + (l & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wg[(16 * bi + (l >> 4) + 4 * r) * NMAX + 16 * bj + (l & 15)] = acc[r];
+    }
+    __syncthreads();
+    d4 gt[MT];
+    int tbi[MT], tbj[MT];
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      const int t = wv + q * NWV;
+      int bj = 0;
+      if (t < NUT) {
+        while ((bj + 1) * (bj + 2) / 2 <= t) ++bj;
+      }
+      tbj[q] = bj;
+      tbi[q] = t < NUT ? t - bj * (bj + 1) / 2 : 0;
+      gt[q] = d4{0.0, 0.0, 0.0, 0.0};
+      if (t < NUT) {
+#pragma unroll 4
+        for (int kk = 0; kk < NMAX / 4; ++kk) {
+          const int kq = 4 * kk + (l >> 4);
+          const double a = Vs[kq * LDV + 16 * tbi[q] + (l & 15)];
+          const double b = Wg[kq * NMAX + 16 * bj + (l & 15)];
+          gt[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gt[q], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      if (wv + q * NWV < NUT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * tbi[q] + (l >> 4) + 4 * r, j = 16 * tbj[q] + (l & 15);
+          if (i <= j) Gp[pk(i, j)] = gt[q][r];
+        }
+      }
+    }
+    __syncthreads();
+  }
 
   const int N2 = n + (n & 1);
   const int M = N2 - 1;
@@ -225,6 +294,10 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     }
     Pd[i * nb + j] = static_cast<T>(s);
     Pd[j * nb + i] = static_cast<T>(s);
+  }
+  for (int idx = tid; idx < nb * nb; idx += NT) {
+    const int i = idx / nb, j = idx - (idx / nb) * nb;
+    d.V[idx] = (i < n && j < n) ? Vs[i * LDV + j] : 0.0;
   }
   if (tid == 0) {
     int rank = 0;

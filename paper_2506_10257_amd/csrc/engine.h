@@ -36,7 +36,7 @@ inline int class_key(const Geo& g) { return g.nb | (g.kind << 8) | (g.prec << 9)
 
 // Byte offsets of one solve's device memory.
 struct Big {
-  size_t S0, S1, Y0, Y1, part, gpart, P, V, state, trace, total;
+  size_t S0, S1, Y0, Y1, part, gpart, P, V, escratch, state, trace, total;
 };
 
 bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g);

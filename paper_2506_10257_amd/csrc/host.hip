@@ -242,6 +242,8 @@ Big big_layout(int64_t m, int64_t n, const Geo& g) {
   b.gpart = o; o += al256(static_cast<size_t>(g.groups) * g.pstride * sizeof(double));
   b.P = o; o += al256(static_cast<size_t>(g.nb) * g.nb * g.es);
   b.V = o; o += al256(static_cast<size_t>(g.nb) * g.nb * sizeof(double));
+  b.escratch = o;
+  if (n > kEigMaxN) o += al256(static_cast<size_t>(kEigWideMaxN) * kEigWideMaxN * sizeof(double));
   b.state = o; o += al256(sizeof(SolveState));
   b.trace = o;
 #ifdef RPCA_TRACE
@@ -313,6 +315,7 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
     d.gpartials = reinterpret_cast<double*>(b + r.big.gpart);
     d.P = b + r.big.P;
     d.V = reinterpret_cast<double*>(b + r.big.V);
+    d.escratch = r.n > kEigMaxN ? reinterpret_cast<double*>(b + r.big.escratch) : nullptr;
     d.st = reinterpret_cast<SolveState*>(b + r.big.state);
 #ifdef RPCA_TRACE
     d.wgtrace = reinterpret_cast<int64_t*>(b + r.big.trace);
