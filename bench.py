@@ -283,13 +283,28 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_copycal(args):
+    """A plain device copy of a known size (256 MiB), repeated: the reference
+    that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy_256MiB", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "copies": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single")
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "copycal"], default="single")
     ap.add_argument("--count", type=int, default=64, help="windows in the batch workload")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=4.0, help="serve: trace length (s)")
@@ -309,6 +324,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "copycal":
+        run_copycal(args)
         return
 
     import numpy as np
