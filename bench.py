@@ -3,14 +3,17 @@
 Workload: the seeded 512x512-pixel x 20-frame ultrasound window (Casorati
 262144 x 20), FP32, lambda = 1/512, tol = 1e-6, maxit = 1000.  One step is
 one complete solve (init pass, every iteration, finalize) with the input
-already resident in HBM.
+already resident in HBM, on the production path (graph-captured iteration
+chunks).
 
 value = sum over timed steps of m * n * iterations / wall time of the steps.
 
 The JSON line also carries
   roofline     : the fused update kernel's algorithmic bytes per launch over
-                 its mean launch time (HIP events on the library's stream,
-                 over the timed steps) against the 8 TB/s HBM peak;
+                 its mean launch time (a HIP event pair per launch on the
+                 library's stream, over a repeat of the timed steps) against
+                 the 8 TB/s HBM peak, and the HBM bytes per launch measured
+                 with rocprofv3 counters (profiles/);
   cpu_baseline : the FP64 CPU oracle timed on a bounded number of iterations
                  of the same window on this host;
   latency      : p50 / p99 of the per-solve wall time.
@@ -33,6 +36,16 @@ METRIC = "RPCA pixel-frames/s per ALM iter; p50/p99 solve latency, 20-frame wind
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_traffic_512x512x20_f32.json")
 KERNEL_SOURCES = ("paper_2506_10257_amd/csrc/stream_impl.h", "paper_2506_10257_amd/csrc/common.h",
                   "paper_2506_10257_amd/csrc/stream_f32.hip")
+
+
+def tuning_summary() -> dict:
+    """Current tuning choices (eigensolver threads per class; classes on the
+    MFMA tile kernel)."""
+    import paper_2506_10257_amd as rp
+    ch = rp.tuning_choices()
+    return {"eig_threads_f32": {str(c): v for (dt, c), v in ch["eig_threads"].items() if dt == rp.RPCA_F32},
+            "eig_threads_f64": {str(c): v for (dt, c), v in ch["eig_threads"].items() if dt == rp.RPCA_F64},
+            "tile_kernel_classes": [c for c, v in ch["stream_kernel"].items() if v == 1]}
 
 
 def kernel_source_sha() -> str:
@@ -165,6 +178,7 @@ def run_batch(args):
                      "kernel": "k_stream<float,NB,false> (all frame classes)",
                      "launches": prof["update_launches"],
                      "measured_on": "one extra step with per-launch HIP events (one stream)"},
+        "tuning": tuning_summary(),
         "kernel_timed_step": {"ms": timed_wall * 1e3,
                               **{k: prof[k] for k in ("init_ms", "eig_ms", "update_ms", "finalize_ms")}},
         "plain": {"value": plain_work / plain_wall, "solves_per_s": len(Ms) / plain_wall,
@@ -274,11 +288,74 @@ def run_serve(args):
         "solves_per_s": len(reqs) / wall,
         "latency_ms": {"p50": float(np.percentile(lat, 50)) * 1e3,
                        "p99": float(np.percentile(lat, 99)) * 1e3},
-        "wall_s": wall, "peak_admitted_gb": peak / 2 ** 30,
+        "wall_s": wall, "peak_admitted_gb": peak / 2 ** 30, "tuning": tuning_summary(),
         "statuses": {str(k): int(v) for k, v in zip(*np.unique(list(status.values()), return_counts=True))},
         "plain": {"value": p_work / p_wall, "solves_per_s": len(reqs) / p_wall, "wall_s": p_wall,
                   "latency_ms": {"p50": float(np.percentile(p_lat, 50)) * 1e3,
                                  "p99": float(np.percentile(p_lat, 99)) * 1e3}},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_precision(args):
+    """1024x1024x40 window (15 dB): the FP32 path against the split-BF16
+    contraction mode.  Throughput of full solves (tol 1e-6, maxit 1000) for
+    both, and the error of each against the FP64 oracle at a fixed iteration
+    count (the oracle's full solve of this window takes hours on a host)."""
+    import numpy as np
+    import torch
+
+    import paper_2506_10257_amd as rp
+    from synth import window_1024x1024x40
+    from oracle import rpca, rel_fro, dice, bound_threshold
+
+    dev = torch.device("cuda:0")
+    w = window_1024x1024x40()
+    X = w.X()
+    m, n = X.shape
+    M = torch.from_numpy(np.ascontiguousarray(X.T.astype(np.float32))).to(dev).t()
+    tol, maxit = 1e-6, 1000
+    modes = {"f32": rp.RPCA_GRAM_DEFAULT, "bf16x3": rp.RPCA_GRAM_BF16X3}
+    out_modes = {}
+    for name, gm in modes.items():
+        for _ in range(args.warmup):
+            rp.solve(M, tol=tol, maxit=maxit, gram_mode=gm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(args.steps):
+            r = rp.solve(M, tol=tol, maxit=maxit, gram_mode=gm)
+            torch.cuda.synchronize()
+            iters += r.iterations
+        wall = time.perf_counter() - t0
+        out_modes[name] = {"value": m * n * iters / wall, "ms_per_solve": wall / args.steps * 1e3,
+                           "iterations": r.iterations, "status": r.status}
+        print(f"[precision] {name}: {out_modes[name]}", file=sys.stderr, flush=True)
+    # error against the oracle at a fixed iteration count
+    K = args.parity_iters
+    ref = rpca(X, tol=0.0, maxit=K)
+    theta = bound_threshold(w.L_gt, w.bound_mask)
+    for name, gm in modes.items():
+        r = rp.solve(M, tol=0.0, maxit=K, gram_mode=gm)
+        Lh = r.L.t().contiguous().cpu().numpy().T.astype(np.float64)
+        Sh = r.S.t().contiguous().cpu().numpy().T.astype(np.float64)
+        out_modes[name]["error_vs_oracle_at_k"] = {
+            "k": K, "relL": rel_fro(Lh, ref.L), "relS": rel_fro(Sh, ref.S),
+            "dice": dice(Lh >= theta, ref.L >= theta)}
+    f32 = out_modes["f32"]
+    out = {
+        "metric": METRIC,
+        "value": f32["value"],
+        "unit": "pixel-frames/s per ALM iter",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_solve"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded ultrasound-shaped window: rank-2 drifting speckle, 800 bound + "
+                "1600 free bubbles on 24 vessels, 15 dB SNR)",
+        "config": {"workload": "rpca_1024x1024x40_precision", "m": m, "n": n, "tol": tol,
+                   "maxit": maxit},
+        "modes": out_modes,
+        "tuning": tuning_summary(),
     }
     print(json.dumps(out), flush=True)
 
@@ -304,7 +381,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--workload", choices=["single", "batch", "serve", "copycal"], default="single")
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "precision", "copycal"],
+                    default="single")
+    ap.add_argument("--parity-iters", type=int, default=5,
+                    help="precision: iterations compared with the oracle")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in tuning choices instead of measuring them first")
     ap.add_argument("--count", type=int, default=64, help="windows in the batch workload")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: arrivals per second")
     ap.add_argument("--duration", type=float, default=4.0, help="serve: trace length (s)")
@@ -328,6 +410,17 @@ def main():
     if args.workload == "copycal":
         run_copycal(args)
         return
+    if not args.no_autotune:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+        import paper_2506_10257_amd as rp
+        dt = rp.RPCA_F64 if args.dtype == "f64" and args.workload == "single" else rp.RPCA_F32
+        rc = rp.rpca_autotune(dt, 262144)
+        if rc != rp.RPCA_OK:
+            print(f"autotune failed ({rc}): {rp.rpca_last_error()}", file=sys.stderr)
+            sys.exit(1)
+    if args.workload == "precision":
+        run_precision(args)
+        return
 
     import numpy as np
     import torch
@@ -348,8 +441,7 @@ def main():
         rp.solve(M, lam=lam, tol=tol, maxit=maxit)
     torch.cuda.synchronize()
 
-    rp.rpca_profile_read(reset=True)
-    rp.rpca_profile_enable(True)
+    # Timed region: the production path (graph-captured iteration chunks).
     times, iters = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -361,16 +453,20 @@ def main():
         iters.append(r.iterations)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    rp.rpca_profile_enable(False)
-    prof = rp.rpca_profile_read(reset=True)
 
-    # The same steps without kernel timing (graph-captured iteration chunks).
-    gtimes = []
+    # Kernel timing: the same steps again with a HIP event pair around every
+    # launch on the launching stream (direct launches, since per-launch
+    # events cannot be read back from a replayed graph chunk).
+    rp.rpca_profile_read(reset=True)
+    rp.rpca_profile_enable(True)
+    ktimes = []
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        rg = rp.solve(M, lam=lam, tol=tol, maxit=maxit)
+        rp.solve(M, lam=lam, tol=tol, maxit=maxit)
         torch.cuda.synchronize()
-        gtimes.append(time.perf_counter() - t0)
+        ktimes.append(time.perf_counter() - t0)
+    rp.rpca_profile_enable(False)
+    prof = rp.rpca_profile_read(reset=True)
 
     value = sum(m * n * k for k in iters) / wall
     upd_ms = prof["update_ms"] / max(prof["update_launches"], 1)
@@ -400,11 +496,12 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_stream<{'float' if args.dtype == 'f32' else 'double'},20,false>",
                      "bytes_per_launch": bytes_per_launch, "mean_launch_us": upd_ms * 1e3,
-                     "launches": prof["update_launches"]},
+                     "launches": prof["update_launches"],
+                     "measured_on": "the same steps repeated with a HIP event pair per launch"},
         "phase_ms_per_solve": {k: prof[k] / max(prof["solves"], 1)
                                for k in ("init_ms", "eig_ms", "update_ms", "finalize_ms")},
-        "graph_path": {"ms_per_step": float(np.mean(gtimes)) * 1e3,
-                       "value": m * n * rg.iterations / float(np.mean(gtimes))},
+        "tuning": tuning_summary(),
+        "kernel_timed_steps": {"ms_per_step": float(np.mean(ktimes)) * 1e3},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, lam)

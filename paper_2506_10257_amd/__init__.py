@@ -27,6 +27,7 @@ __all__ = ["solve", "solve_many", "SolveResult", "casorati_shape", "rpca_solve_f
            "rpca_solve_f64", "rpca_solve_many", "rpca_solve_ex", "rpca_footprint_bytes",
            "rpca_strerror", "rpca_version", "rpca_last_error", "rpca_profile_enable", "rpca_profile_read",
            "rpca_tune_set", "rpca_tune_get", "RPCA_KNOB_EIG_THREADS", "RPCA_KNOB_STREAM_KERNEL", "Server",
+           "rpca_autotune", "rpca_autotune_save", "rpca_autotune_load", "tuning_choices",
            "RPCA_OK", "RPCA_NOT_CONVERGED", "RPCA_ERR_ARG", "RPCA_ERR_NOMEM",
            "RPCA_ERR_DEVICE", "RPCA_ERR_NONFINITE", "RPCA_ERR_UNSUPPORTED", "RPCA_F32",
            "RPCA_F64", "RPCA_GRAM_DEFAULT", "RPCA_GRAM_BF16X3", "RPCA_N_MAX"]
@@ -146,6 +147,33 @@ def rpca_tune_set(knob: int, dtype: int, cls: int, value: int) -> int:
 
 def rpca_tune_get(knob: int, dtype: int, cls: int) -> int:
     return int(_lib.load().rpca_tune_get(int(knob), int(dtype), int(cls)))
+
+
+def rpca_autotune(dtype: int, rows: int = 262144, stream: Optional[int] = None) -> int:
+    """Time every tuning variant on this device and keep the fastest."""
+    if stream is None:
+        import torch
+        stream = int(torch.cuda.current_stream().cuda_stream)
+    return int(_lib.load().rpca_autotune(int(dtype), int(rows), stream))
+
+
+def rpca_autotune_save(path: str) -> int:
+    return int(_lib.load().rpca_autotune_save(str(path).encode()))
+
+
+def rpca_autotune_load(path: str) -> int:
+    return int(_lib.load().rpca_autotune_load(str(path).encode()))
+
+
+def tuning_choices() -> dict:
+    """Current knob values: {"eig_threads": {(dtype, cls): v}, "stream_kernel": {cls: v}}."""
+    out = {"eig_threads": {}, "stream_kernel": {}}
+    for dt in (RPCA_F64, RPCA_F32):
+        for cls in (16, 32, 64):
+            out["eig_threads"][(dt, cls)] = rpca_tune_get(RPCA_KNOB_EIG_THREADS, dt, cls)
+    for cls in (4, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 56, 60, 64):
+        out["stream_kernel"][cls] = rpca_tune_get(RPCA_KNOB_STREAM_KERNEL, RPCA_F32, cls)
+    return out
 
 
 @dataclass

@@ -34,6 +34,7 @@ EXPORTS = (
     "rpca_tune_set", "rpca_tune_get",
     "rpca_server_create", "rpca_server_submit", "rpca_server_step", "rpca_server_pending",
     "rpca_server_peak_bytes", "rpca_server_request_bytes", "rpca_server_destroy",
+    "rpca_autotune", "rpca_autotune_save", "rpca_autotune_load",
 )
 
 
@@ -137,5 +138,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpca_server_request_bytes.restype = sz
     lib.rpca_server_destroy.argtypes = [vp]
     lib.rpca_server_destroy.restype = None
+    lib.rpca_autotune.argtypes = [i32, i64, vp]
+    lib.rpca_autotune.restype = ctypes.c_int
+    lib.rpca_autotune_save.argtypes = [ctypes.c_char_p]
+    lib.rpca_autotune_save.restype = ctypes.c_int
+    lib.rpca_autotune_load.argtypes = [ctypes.c_char_p]
+    lib.rpca_autotune_load.restype = ctypes.c_int
     _lib = lib
     return lib

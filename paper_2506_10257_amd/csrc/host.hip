@@ -172,8 +172,16 @@ void set_error_text(const char* text) { std::snprintf(g_last_error, sizeof(g_las
 namespace {
 // Streaming kernel per FP32 register frame class (index: class value 0..64):
 // 0 = register kernel, 1 = MFMA tile kernel.  Classes above 64 frames and the
-// split-BF16 mode always use the MFMA tile kernel.
+// split-BF16 mode always use the MFMA tile kernel.  Defaults from timing on
+// MI355X: the register kernel up to 32 frames, the tile kernel from 40 (at
+// 60 frames the register kernel's FMA chains and partial reductions leave it
+// at 2 TB/s against 3.2 TB/s for the tile kernel).
 std::atomic<int> g_stream_kernel[kEigMaxN + 1];
+struct StreamKernelDefaults {
+  StreamKernelDefaults() {
+    for (int c = 0; c <= kEigMaxN; ++c) g_stream_kernel[c].store(c >= 40 ? 1 : 0);
+  }
+} g_stream_kernel_defaults;
 }  // namespace
 
 int nb_class(int64_t n, int dtype) {

@@ -4,9 +4,10 @@
 //
 // A workgroup (8 wavefronts) walks a contiguous run of 64-row tiles of one
 // solve.  Per tile:
-//   1. load X, S, Y coalesced (lane = pixel row, wave w takes frames w, w+8,
-//      ...), keep X and Y in registers and put A = X - S + Y/mu into an LDS
-//      tile stored frame-major;
+//   1. load X, S, Y coalesced (lane = pixel row, wave w takes frames w,
+//      w + waves, ...), keep X and Y in registers and put A = X - S + Y/mu
+//      into an LDS tile stored frame-major; the next tile's loads are issued
+//      right after, so they are in flight during the contractions;
 //   2. rebuild L^T = P A^T on the matrix cores into a second LDS tile (P is
 //      symmetric); wave w owns output frame block w and keeps its rows of P
 //      in registers for the whole launch;
@@ -14,7 +15,7 @@
 //      step (shrink, dual update, residual, next A) exactly as the register
 //      kernel does; the next A overwrites the A tile;
 //   4. accumulate the Gram A'^T A' of the tile on the matrix cores; wave w
-//      owns every 8th 16 x 16 output block (upper triangle) and keeps it in
+//      owns every NW-th 16 x 16 output block (upper triangle) and keeps it in
 //      registers across the tiles of the workgroup.
 // The workgroup writes one partial (scalars and Gram, in the 4 x 4 block
 // layout of the other streaming kernels) at the end, so the reduction and
@@ -39,9 +40,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int R = kWideRows;  // rows per tile
-constexpr int LDA = R + 1;    // frame-major LDS tiles: odd stride spreads the banks
-constexpr int NW = 8;         // wavefronts per workgroup
-constexpr int NTH = NW * 64;
+// Frame-major LDS tiles with a row stride of 81 = 17 (mod 32): both MFMA
+// operand patterns (16 frames x 4 rows and 4 frames x 16 rows per wave) then
+// fall in distinct banks within each half-wave.
+constexpr int LDA = R + 17;
+// Wavefronts per workgroup.  (16 waves above 64 frames were measured slower:
+// the 128-register cap of 1024-thread workgroups makes them spill.)
+__host__ __device__ constexpr int waves_for(int) { return 8; }
 
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
@@ -55,9 +60,11 @@ __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
 }
 
 template <int NB, int PHASE, int PREC>
-__global__ void __launch_bounds__(NTH)
+__global__ void __launch_bounds__(waves_for(NB) * 64)
 k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
   static_assert(NB % 16 == 0 && NB <= 128, "frame class");
+  constexpr int NW = waves_for(NB);
+  constexpr int NTH = NW * 64;
   constexpr int NQ = NB / NW;                           // frames per thread
   constexpr int NK4 = NB / 4;                           // f32 k-steps of the rebuild
   constexpr int NT16 = NB / 16;                         // 16-frame blocks
@@ -168,36 +175,67 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
       return;
     }
   }
-  for (int tile = t0; tile < t1; ++tile) {
+  // Raw loads of one tile: X, and S_{k-1}, Y_{k-1} after the first iteration.
+  const bool read_sy = !INIT && k >= 1 && !first;
+  auto load_tile = [&](int tile, float* xr, float* sr, float* yr) {
     const int64_t p = static_cast<int64_t>(tile) * R + l;
-    const bool valid = p < m;
-    float x[NQ], y[NQ];
-    // 1. load, A tile
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int j = w + NW * q;
-      x[q] = 0.f;
-      y[q] = 0.f;
+      xr[q] = 0.f;
+      sr[q] = 0.f;
+      yr[q] = 0.f;
+      if (j < n && p < m) {
+        const size_t off = static_cast<size_t>(j) * static_cast<size_t>(m) + static_cast<size_t>(p);
+        xr[q] = X[off];
+        if (read_sy) {
+          sr[q] = Sin[off];
+          yr[q] = Yin[off];
+        }
+      }
+    }
+  };
+  // With few frames per thread the next tile's loads are issued before the
+  // current tile's contractions, so they are in flight meanwhile.
+  constexpr bool PF = NQ <= 10;
+  float xn[PF ? NQ : 1], sn_[PF ? NQ : 1], yn[PF ? NQ : 1];
+  if constexpr (PF) {
+    if (t0 < t1) load_tile(t0, xn, sn_, yn);
+  }
+  for (int tile = t0; tile < t1; ++tile) {
+    const int64_t p = static_cast<int64_t>(tile) * R + l;
+    const bool valid = p < m;
+    float x[NQ], y[NQ], sv[NQ];
+    // 1. load, A tile
+    if constexpr (PF) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        x[q] = xn[q];
+        sv[q] = sn_[q];
+        y[q] = yn[q];
+      }
+    } else {
+      load_tile(tile, x, sv, y);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int j = w + NW * q;
       float a = 0.f;
       if (j < n && valid) {
-        const size_t off = static_cast<size_t>(j) * static_cast<size_t>(m) + static_cast<size_t>(p);
-        x[q] = X[off];
         if constexpr (INIT) {
           const double xd = static_cast<double>(x[q]);
           s1 += fabs(xd);
           s2 = fma(xd, xd, s2);
           nf += __builtin_isfinite(x[q]) ? 0.0 : 1.0;
           a = x[q];
-        } else if (k >= 1) {
-          float s = 0.f;
-          if (!first) {
-            s = Sin[off];
-            y[q] = Yin[off];
-          }
-          a = fmaf(y[q], imu, x[q] - s);
+        } else {
+          a = fmaf(y[q], imu, x[q] - sv[q]);
         }
       }
       At[j * LDA + l] = a;
+    }
+    if constexpr (PF) {
+      if (tile + 1 < t1) load_tile(tile + 1, xn, sn_, yn);
     }
     __syncthreads();
 
@@ -351,7 +389,7 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
 hipError_t launch_wide(int nb, int mode, int prec, int grid, hipStream_t stream,
                        const SolveDesc* descs, const WorkItem* items) {
   if (grid <= 0) return hipSuccess;
-  const dim3 g(grid), b(NTH);
+  const dim3 g(grid), b(waves_for(nb) * 64);
 #define RPCA_WIDE(N, P)                                                                        \
   if (nb == N && prec == P) {                                                                  \
     if (mode == kModeInit)                                                                     \

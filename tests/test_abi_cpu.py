@@ -138,3 +138,28 @@ def test_stream_kernel_knob(lib):
     assert rp.rpca_tune_set(K, rp.RPCA_F32, 40, 2) == rp.RPCA_ERR_ARG
     assert rp.rpca_tune_set(K, rp.RPCA_F64, 20, 1) == rp.RPCA_ERR_ARG
     assert rp.rpca_tune_get(K, rp.RPCA_F64, 20) == rp.RPCA_ERR_ARG
+
+
+def test_autotune_save_load_roundtrip(lib, tmp_path):
+    import paper_2506_10257_amd as rp
+    K, S = rp.RPCA_KNOB_EIG_THREADS, rp.RPCA_KNOB_STREAM_KERNEL
+    before = rp.tuning_choices()
+    path = tmp_path / "tune.txt"
+    assert rp.rpca_autotune_save(str(path)) == rp.RPCA_OK
+    try:
+        rp.rpca_tune_set(K, rp.RPCA_F32, 64, 256)
+        rp.rpca_tune_set(S, rp.RPCA_F32, 40, 1 - before["stream_kernel"][40])
+        assert rp.tuning_choices() != before
+        assert rp.rpca_autotune_load(str(path)) == rp.RPCA_OK
+        assert rp.tuning_choices() == before
+        # a bad line is reported, the valid ones are still applied
+        bad = tmp_path / "bad.txt"
+        bad.write_text(f"{S} {rp.RPCA_F32} 40 {1 - before['stream_kernel'][40]}\n9 9 9 9\n")
+        assert rp.rpca_autotune_load(str(bad)) == rp.RPCA_ERR_ARG
+        assert rp.rpca_tune_get(S, rp.RPCA_F32, 40) == 1 - before["stream_kernel"][40]
+        assert rp.rpca_autotune_load(str(tmp_path / "missing.txt")) == rp.RPCA_ERR_ARG
+        assert lib.rpca_autotune(7, 4096, None) == rp.RPCA_ERR_ARG
+        assert lib.rpca_autotune(rp.RPCA_F32, 10, None) == rp.RPCA_ERR_ARG
+    finally:
+        rp.rpca_autotune_load(str(path))
+    assert rp.tuning_choices() == before

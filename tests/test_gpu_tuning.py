@@ -35,3 +35,18 @@ def test_eig_threads_bitwise(n, cls, dtype):
     for nt, r in outs[1:]:
         assert r.iterations == r0.iterations, nt
         assert bool((r.L == r0.L).all()) and bool((r.S == r0.S).all()), nt
+
+
+def test_autotune_runs_and_keeps_valid_choices(tmp_path):
+    device()
+    saved = tmp_path / "before.txt"
+    assert rp.rpca_autotune_save(str(saved)) == rp.RPCA_OK
+    try:
+        assert rp.rpca_autotune(rp.RPCA_F32, 65536) == rp.RPCA_OK, rp.rpca_last_error()
+        assert rp.rpca_autotune(rp.RPCA_F64, 65536) == rp.RPCA_OK, rp.rpca_last_error()
+        ch = rp.tuning_choices()
+        assert all(v in (256, 512, 1024) for v in ch["eig_threads"].values())
+        assert all(v in (0, 1) for v in ch["stream_kernel"].values())
+        print("[tuning]", ch, flush=True)
+    finally:
+        rp.rpca_autotune_load(str(saved))

@@ -119,3 +119,22 @@ def test_bf16x3_error_stated(H, W, n):
     report(f"bf16x3 {H}x{W}x{n}", it=it, it_ref=ref.iterations, relL=eL, relS=eS, dice=d)
     assert eL <= 2e-2 and eS <= 2e-2
     assert d >= 0.99
+
+
+def test_precision_window_fp32_and_bf16x3():
+    """A scaled-down window of the 1024x1024x40 precision workload (same
+    density and 15 dB SNR): FP32 within the bar, split-BF16 error stated."""
+    from synth import make_window, density_counts
+    device()
+    nb, nf, nv = density_counts(128, 128)
+    w = make_window(128, 128, 40, nb, nf, nv, 15.0, 7501)
+    X = w.X()
+    ref = rpca(X, tol=1e-6, maxit=1000)
+    L, S, it, rc = _solve(X, tol=1e-6, maxit=1000)
+    _check("precision 128x128x40 f32", w, ref, L, S, it)
+    L, S, it, rc = _solve(X, gram_mode=rp.RPCA_GRAM_BF16X3, tol=1e-6, maxit=1000)
+    theta = bound_threshold(w.L_gt, w.bound_mask)
+    eL, eS = rel_fro(L, ref.L), rel_fro(S, ref.S)
+    d = dice(L >= theta, ref.L >= theta)
+    report("precision 128x128x40 bf16x3", it=it, it_ref=ref.iterations, relL=eL, relS=eS, dice=d)
+    assert eL <= 2e-2 and eS <= 2e-2 and d >= 0.99
