@@ -253,6 +253,30 @@ size_t rpca_server_request_bytes(int64_t m, int64_t n, int32_t dtype);
 /* Wait for device work, free every workspace and drop queued requests. */
 void rpca_server_destroy(rpca_server* s);
 
+/*
+ * Autotuning: choose every tuning knob by measurement on the current device.
+ *
+ * rpca_autotune runs short solves (tol = 0, a dozen iterations) of synthetic
+ * windows through the library with kernel timing on, for each variant of
+ * each knob, and keeps the fastest:
+ *   - RPCA_KNOB_EIG_THREADS per eigensolver class, on a 16384 x cls window;
+ *   - RPCA_KNOB_STREAM_KERNEL per FP32 register class of 16 frames or more,
+ *     on a `rows` x cls window (rows >= 256; e.g. 262144 for 512 x 512
+ *     images).
+ * It allocates its windows with hipMalloc and frees them before returning.
+ * It uses the kernel-timing accumulators (rpca_profile_*), which it resets,
+ * so it must not run while other calls use them.  Returns RPCA_OK, or the
+ * first failing solve's code (that knob keeps its previous value).
+ *
+ * rpca_autotune_save writes the current choices to a text file, one
+ * "knob dtype class value" line each; rpca_autotune_load applies such a
+ * file.  Both return RPCA_OK, or RPCA_ERR_ARG when the file cannot be
+ * opened or a line is invalid (load still applies every valid line).
+ */
+int rpca_autotune(int32_t dtype, int64_t rows, void* stream);
+int rpca_autotune_save(const char* path);
+int rpca_autotune_load(const char* path);
+
 /* Static description of a status code. */
 const char* rpca_strerror(int code);
 
