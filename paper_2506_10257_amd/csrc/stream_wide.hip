@@ -9,8 +9,9 @@
 //      into an LDS tile stored frame-major; the next tile's loads are issued
 //      right after, so they are in flight during the contractions;
 //   2. rebuild L^T = P A^T on the matrix cores into a second LDS tile (P is
-//      symmetric); wave w owns output frame block w and keeps its rows of P
-//      in registers for the whole launch;
+//      symmetric); each 16-frame output block is shared by NW / NT16 waves
+//      (by 16-row blocks), which keep their rows of P in registers for the
+//      whole launch;
 //   3. read back each thread's L entries and apply the fused elementwise
 //      step (shrink, dual update, residual, next A) exactly as the register
 //      kernel does; the next A overwrites the A tile;
@@ -111,15 +112,18 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   // zero the padding frames of the A tile once (never written afterwards)
   for (int idx = NB * LDA + tid; idx < NBK * LDA; idx += NTH) At[idx] = 0.f;
 
-  // Rebuild operands: wave w owns frame block t = w.
+  // Rebuild work: frame block t = w mod NT16 and every NREP-th 16-row block
+  // of the tile starting at w / NT16, so all waves share the rebuild when the
+  // class has fewer frame blocks than waves.
   constexpr int NOWN = 1;
+  constexpr int NREP = NW / NT16;
   float pa[PREC ? 1 : NOWN][PREC ? 1 : NK4];
   bf8 ph[PREC ? NOWN : 1][PREC ? NKB : 1], pl[PREC ? NOWN : 1][PREC ? NKB : 1];
   if constexpr (!INIT) {
     const gptr<const float> P = as_global<float>(static_cast<const void*>(d.P));
 #pragma unroll
     for (int o = 0; o < NOWN; ++o) {
-      const int t = w + NW * o;
+      const int t = w % NT16 + NW * o;
       const int prow = 16 * (t < NT16 ? t : 0) + (l & 15);
       if constexpr (PREC == 0) {
 #pragma unroll
@@ -243,10 +247,10 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
       // 2. rebuild L^T = P A^T into Lt
 #pragma unroll
       for (int o = 0; o < NOWN; ++o) {
-        const int t = w + NW * o;
-        if (t < NT16) {
+        const int t = w % NT16 + NW * o;
+        if (w < NT16 * NREP) {
 #pragma unroll 1
-          for (int rb = 0; rb < R / 16; ++rb) {
+          for (int rb = w / NT16; rb < R / 16; rb += NREP) {
             f4 acc = {0.f, 0.f, 0.f, 0.f};
             if constexpr (PREC == 0) {
 #pragma unroll
