@@ -299,7 +299,7 @@ def run_serve(args):
 
 def run_precision(args):
     """1024x1024x40 window (15 dB): the FP32 path against the split-BF16
-    contraction mode.  Throughput of full solves (tol 1e-6, maxit 1000) for
+    contraction modes (two- and three-way splits).  Throughput of full solves (tol 1e-6, maxit 1000) for
     both, and the error of each against the FP64 oracle at a fixed iteration
     count (the oracle's full solve of this window takes hours on a host)."""
     import numpy as np
@@ -315,7 +315,8 @@ def run_precision(args):
     m, n = X.shape
     M = torch.from_numpy(np.ascontiguousarray(X.T.astype(np.float32))).to(dev).t()
     tol, maxit = 1e-6, 1000
-    modes = {"f32": rp.RPCA_GRAM_DEFAULT, "bf16x3": rp.RPCA_GRAM_BF16X3}
+    modes = {"f32": rp.RPCA_GRAM_DEFAULT, "bf16x3": rp.RPCA_GRAM_BF16X3,
+             "bf16x6": rp.RPCA_GRAM_BF16X6}
     out_modes = {}
     for name, gm in modes.items():
         for _ in range(args.warmup):

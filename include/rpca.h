@@ -69,6 +69,10 @@ extern "C" {
                                 eigensolve and thresholding stay FP64.  Less
                                 accurate than the default: see the stated
                                 error of each result                         */
+#define RPCA_GRAM_BF16X6  2  /* F32 only: as BF16X3 with the three-way split
+                                x = hi + mid + lo and the six products of
+                                order >= 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo,
+                                mid*mid, lo*hi): about FP32 accuracy          */
 
 #define RPCA_N_MAX 112   /* largest frame count n accepted (the FP64 eigensolve
                             of the n x n Gram keeps G and V in 160 KB of LDS);
@@ -122,8 +126,8 @@ typedef struct rpca_problem {
  * launches, so the FP64 eigensolves of different problems overlap each other
  * and the streaming passes fill the whole GPU.  Each problem's result is
  * bitwise identical to the same problem solved alone with rpca_solve_*.
- * dtype: RPCA_F64 or RPCA_F32.  gram_mode: RPCA_GRAM_DEFAULT or
- * RPCA_GRAM_BF16X3 (RPCA_F32 only).  Returns the worst status over the
+ * dtype: RPCA_F64 or RPCA_F32.  gram_mode: RPCA_GRAM_DEFAULT, or
+ * RPCA_GRAM_BF16X3 / RPCA_GRAM_BF16X6 (RPCA_F32 only).  Returns the worst status over the
  * problems (negative codes first) and records each problem's own status.
  */
 int rpca_solve_many(rpca_problem* probs, int32_t count, int32_t dtype,
@@ -227,8 +231,9 @@ int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls);
  * flags: 0, or RPCA_SERVER_SIMULATE to run the admission logic without any
  * device work (every request then completes after maxit iterations with
  * RPCA_NOT_CONVERGED and residual 0).  create returns NULL for an invalid
- * argument (dtype, gram_mode other than RPCA_GRAM_DEFAULT, a zero budget,
- * max_active < 1, quantum < 1, unknown flags).
+ * argument (dtype, an unknown gram_mode or a split-BF16 mode with RPCA_F64,
+ * a zero budget, max_active < 1, quantum < 1, unknown flags).  Every
+ * request of a server uses the server's dtype and gram_mode.
  */
 typedef struct rpca_server rpca_server;
 typedef struct rpca_completion {

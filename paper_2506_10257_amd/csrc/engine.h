@@ -27,7 +27,7 @@ namespace rpca {
 struct Geo {
   int nb = 0, tiles = 0, tps = 1, slots = 0, groups = 0, pstride = 0;
   int kind = 0;  // streaming kernel: 0 register (thread per row), 1 MFMA tiles
-  int prec = 0;  // contraction precision: 0 storage/FP64, 1 split-BF16
+  int prec = 0;  // contraction precision: 0 storage/FP64, 1 BF16x3, 2 BF16x6
   size_t es = 0;
 };
 

@@ -121,7 +121,7 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 // `key` is a class key (class_key): frame class, kernel kind and precision.
 hipError_t launch_stream(int dtype, int key, int mode, int grid, hipStream_t s, const SolveDesc* d,
                          const WorkItem* it) {
-  const int nb = key & 0xff, kind = (key >> 8) & 1, prec = (key >> 9) & 1;
+  const int nb = key & 0xff, kind = (key >> 8) & 1, prec = (key >> 9) & 3;
   if (kind == 1) return launch_wide(nb, mode, prec, grid, s, d, it);
   return dtype == RPCA_F32 ? launch_stream_f32(nb, mode, grid, s, d, it)
                            : launch_stream_f64(nb, mode, grid, s, d, it);
@@ -212,7 +212,7 @@ bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g) {
   if (m < 1 || n < 1 || n > RPCA_N_MAX) return false;
   if (m >= (int64_t(1) << 30)) return false;  // row offsets are 32-bit byte offsets
   g.es = dtype == RPCA_F32 ? 4 : 8;
-  g.prec = gram_mode == RPCA_GRAM_BF16X3 ? 1 : 0;
+  g.prec = gram_mode == RPCA_GRAM_BF16X3 ? 1 : (gram_mode == RPCA_GRAM_BF16X6 ? 2 : 0);
   if (g.prec && dtype != RPCA_F32) return false;
   const int reg = nb_class(n, dtype);
   g.kind = 1;
@@ -584,8 +584,10 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   g_last_error[0] = '\0';
   if (count < 1 || probs == nullptr) return RPCA_ERR_ARG;
   if (dtype != RPCA_F32 && dtype != RPCA_F64) return RPCA_ERR_ARG;
-  if (gram_mode != RPCA_GRAM_DEFAULT && gram_mode != RPCA_GRAM_BF16X3) return RPCA_ERR_ARG;
-  if (gram_mode == RPCA_GRAM_BF16X3 && dtype != RPCA_F32) return RPCA_ERR_ARG;
+  if (gram_mode != RPCA_GRAM_DEFAULT && gram_mode != RPCA_GRAM_BF16X3 &&
+      gram_mode != RPCA_GRAM_BF16X6)
+    return RPCA_ERR_ARG;
+  if (gram_mode != RPCA_GRAM_DEFAULT && dtype != RPCA_F32) return RPCA_ERR_ARG;
 
   std::vector<SolveRec> recs(count);
   for (int i = 0; i < count; ++i) {

@@ -286,8 +286,10 @@ size_t rpca_server_request_bytes(int64_t m, int64_t n, int32_t dtype) {
 rpca_server* rpca_server_create(int32_t dtype, int32_t gram_mode, size_t hbm_budget,
                                 int32_t max_active, int32_t quantum, int32_t flags, void* stream) {
   if (dtype != RPCA_F32 && dtype != RPCA_F64) return nullptr;
-  if (gram_mode != RPCA_GRAM_DEFAULT && gram_mode != RPCA_GRAM_BF16X3) return nullptr;
-  if (gram_mode == RPCA_GRAM_BF16X3 && dtype != RPCA_F32) return nullptr;
+  if (gram_mode != RPCA_GRAM_DEFAULT && gram_mode != RPCA_GRAM_BF16X3 &&
+      gram_mode != RPCA_GRAM_BF16X6)
+    return nullptr;
+  if (gram_mode != RPCA_GRAM_DEFAULT && dtype != RPCA_F32) return nullptr;
   if (hbm_budget == 0 || max_active < 1 || quantum < 1) return nullptr;
   if (flags & ~RPCA_SERVER_SIMULATE) return nullptr;
   rpca_server* s = new (std::nothrow) rpca_server();

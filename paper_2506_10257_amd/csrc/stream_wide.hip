@@ -29,7 +29,10 @@
 //   1  both contractions as three BF16 products, hi*hi + hi*lo + lo*hi of the
 //      split x = hi + lo (hi = bf16(x), lo = bf16(x - hi)), on
 //      v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the Gram is
-//      accumulated in FP32 over each 64-row tile and in FP64 across tiles.
+//      accumulated in FP32 over each 64-row tile and in FP64 across tiles;
+//   2  the same with the three-way split x = hi + mid + lo and the six
+//      products whose order is at most 2^-16 relative to hi*hi (hi*hi,
+//      hi*mid, mid*hi, hi*lo, mid*mid, lo*hi): about FP32 accuracy.
 #include "common.h"
 #include "launch.h"
 
@@ -60,6 +63,44 @@ __device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = static_cast<__bf16>(x - static_cast<float>(hi));
 }
 
+__device__ inline void split3_bf16(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
+  hi = static_cast<__bf16>(x);
+  const float r = x - static_cast<float>(hi);
+  mid = static_cast<__bf16>(r);
+  lo = static_cast<__bf16>(r - static_cast<float>(mid));
+}
+
+// Accumulate the split product sum of one 16x16x32 block: three products of
+// the two-way split (X6 = false) or six of the three-way split, smallest
+// terms first.
+template <bool X6>
+__device__ inline f4 mfma_split(const bf8& ah, const bf8& am, const bf8& al, const bf8& bh,
+                                const bf8& bm, const bf8& bl, f4 acc) {
+  if constexpr (X6) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc, 0, 0, 0);
+  } else {
+    (void)am;
+    (void)bm;
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+template <bool X6>
+__device__ inline void split_any(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
+  if constexpr (X6) {
+    split3_bf16(x, hi, mid, lo);
+  } else {
+    split_bf16(x, hi, lo);
+    mid = static_cast<__bf16>(0.0f);
+  }
+}
+
 template <int NB, int PHASE, int PREC>
 __global__ void __launch_bounds__(waves_for(NB) * 64)
 k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
@@ -69,6 +110,7 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   constexpr int NQ = NB / NW;                           // frames per thread
   constexpr int NK4 = NB / 4;                           // f32 k-steps of the rebuild
   constexpr int NT16 = NB / 16;                         // 16-frame blocks
+  constexpr bool X6 = PREC == 2;
   constexpr int NBK = PREC ? (NB + 31) / 32 * 32 : NB;  // contraction length of the rebuild
   constexpr int NKB = NBK / 32;                         // bf16 k-steps of the rebuild
   constexpr int NGT = NT16 * (NT16 + 1) / 2;            // Gram output blocks (upper)
@@ -119,6 +161,7 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   constexpr int NREP = NW / NT16;
   float pa[PREC ? 1 : NOWN][PREC ? 1 : NK4];
   bf8 ph[PREC ? NOWN : 1][PREC ? NKB : 1], pl[PREC ? NOWN : 1][PREC ? NKB : 1];
+  bf8 pm[X6 ? NOWN : 1][X6 ? NKB : 1];
   if constexpr (!INIT) {
     const gptr<const float> P = as_global<float>(static_cast<const void*>(d.P));
 #pragma unroll
@@ -135,10 +178,11 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
           for (int e = 0; e < 8; ++e) {
             const int col = 32 * kk + 8 * (l >> 4) + e;
             const float v = col < NB ? P[prow * NB + col] : 0.f;
-            __bf16 h, lo;
-            split_bf16(v, h, lo);
+            __bf16 h, md, lo;
+            split_any<X6>(v, h, md, lo);
             ph[o][kk][e] = h;
             pl[o][kk][e] = lo;
+            if constexpr (X6) pm[o][kk][e] = md;
           }
         }
       }
@@ -261,18 +305,17 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
             } else {
 #pragma unroll
               for (int kk = 0; kk < NKB; ++kk) {
-                bf8 bh, bl;
+                bf8 bh, bm, bl;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                   const float v = At[(32 * kk + 8 * (l >> 4) + e) * LDA + 16 * rb + (l & 15)];
-                  __bf16 h, lo;
-                  split_bf16(v, h, lo);
+                  __bf16 h, md, lo;
+                  split_any<X6>(v, h, md, lo);
                   bh[e] = h;
+                  bm[e] = md;
                   bl[e] = lo;
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pl[o][kk], bh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[o][kk], bl, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ph[o][kk], bh, acc, 0, 0, 0);
+                acc = mfma_split<X6>(ph[o][kk], X6 ? pm[o][kk] : bm, pl[o][kk], bh, bm, bl, acc);
               }
             }
 #pragma unroll
@@ -329,20 +372,20 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
             f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kk = 0; kk < R / 32; ++kk) {
-              bf8 ah, al, bh, bl;
+              bf8 ah, am, al, bh, bm, bl;
 #pragma unroll
               for (int e = 0; e < 8; ++e) {
-                __bf16 h, lo;
-                split_bf16(u[32 * kk + 8 * (l >> 4) + e], h, lo);
+                __bf16 h, md, lo;
+                split_any<X6>(u[32 * kk + 8 * (l >> 4) + e], h, md, lo);
                 ah[e] = h;
+                am[e] = md;
                 al[e] = lo;
-                split_bf16(v[32 * kk + 8 * (l >> 4) + e], h, lo);
+                split_any<X6>(v[32 * kk + 8 * (l >> 4) + e], h, md, lo);
                 bh[e] = h;
+                bm[e] = md;
                 bl[e] = lo;
               }
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-              acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+              acc = mfma_split<X6>(ah, am, al, bh, bm, bl, acc);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) gacc[g][r] += static_cast<double>(acc[r]);
@@ -408,6 +451,8 @@ hipError_t launch_wide(int nb, int mode, int prec, int grid, hipStream_t stream,
   RPCA_WIDE(80, 0) RPCA_WIDE(96, 0) RPCA_WIDE(112, 0)
   RPCA_WIDE(16, 1) RPCA_WIDE(32, 1) RPCA_WIDE(48, 1) RPCA_WIDE(64, 1)
   RPCA_WIDE(80, 1) RPCA_WIDE(96, 1) RPCA_WIDE(112, 1)
+  RPCA_WIDE(16, 2) RPCA_WIDE(32, 2) RPCA_WIDE(48, 2) RPCA_WIDE(64, 2)
+  RPCA_WIDE(80, 2) RPCA_WIDE(96, 2) RPCA_WIDE(112, 2)
 #undef RPCA_WIDE
   return hipErrorInvalidValue;
 }

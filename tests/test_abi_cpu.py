@@ -122,6 +122,8 @@ def test_frame_limits(lib):
     p = _lib.RpcaProblem()
     p.M, p.L, p.S, p.m, p.n, p.maxit = A, B, C, 100, 4, 10
     assert lib.rpca_solve_ex(ctypes.byref(p), _lib.RPCA_F64, _lib.RPCA_GRAM_BF16X3, None) == _lib.RPCA_ERR_ARG
+    assert lib.rpca_solve_ex(ctypes.byref(p), _lib.RPCA_F64, _lib.RPCA_GRAM_BF16X6, None) == _lib.RPCA_ERR_ARG
+    assert lib.rpca_solve_ex(ctypes.byref(p), _lib.RPCA_F32, 3, None) == _lib.RPCA_ERR_ARG
 
 
 def test_stream_kernel_knob(lib):

@@ -138,3 +138,16 @@ def test_precision_window_fp32_and_bf16x3():
     d = dice(L >= theta, ref.L >= theta)
     report("precision 128x128x40 bf16x3", it=it, it_ref=ref.iterations, relL=eL, relS=eS, dice=d)
     assert eL <= 2e-2 and eS <= 2e-2 and d >= 0.99
+
+
+@pytest.mark.parametrize("H,W,n", [(128, 128, 40), (48, 50, 100), (64, 72, 20)])
+def test_bf16x6_meets_fp32_bar(H, W, n):
+    """Three-way split BF16 contractions (six products): held to the FP32 bar."""
+    from synth import make_window, density_counts
+    device()
+    nb, nf, nv = density_counts(H, W)
+    w = make_window(H, W, n, nb, nf, nv, 15.0, 7600 + n)
+    X = w.X()
+    ref = rpca(X, tol=1e-6, maxit=1000)
+    L, S, it, rc = _solve(X, gram_mode=rp.RPCA_GRAM_BF16X6, tol=1e-6, maxit=1000)
+    _check(f"bf16x6 {H}x{W}x{n}", w, ref, L, S, it)
