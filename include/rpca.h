@@ -107,6 +107,15 @@ int rpca_solve_f32(const float* M, int64_t m, int64_t n, double lambda, double m
  * RPCA_F32, double for RPCA_F64).  iterations, status and residual are
  * written back by the library (host memory).  residual is the final
  * ||M - L - S||_F / ||M||_F.
+ *
+ * Warm start (sliding windows): S0 and Y0 give the iteration's starting S
+ * and Y instead of zero (either may be NULL for zero); Y, when not NULL,
+ * receives the final dual variable.  The iteration from a given start is
+ * the same ALM iteration (Eqs. 4-6); consecutive overlapping windows can
+ * pass the previous window's S and Y, shifted by the window step, to start
+ * near the solution.  mu (and lambda) default from M as always; S0 and Y0
+ * must be finite and must not overlap L, S or Y.  When sum|M| == 0 the
+ * result is L = S = 0 (and Y = 0) after 0 iterations, as for a cold start.
  */
 typedef struct rpca_problem {
     const void* M;
@@ -118,6 +127,10 @@ typedef struct rpca_problem {
     int32_t iterations;   /* out */
     int32_t status;       /* out */
     double residual;      /* out */
+    /* Optional (NULL when unused), device m x n in the layout of M: */
+    const void* S0;       /* starting S (default 0); read once, not modified */
+    const void* Y0;       /* starting dual Y (default 0); read once */
+    void* Y;              /* out: the final dual Y */
 } rpca_problem;
 
 /*

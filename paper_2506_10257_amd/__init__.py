@@ -183,9 +183,10 @@ class SolveResult:
     iterations: int
     status: int
     residual: float
+    Y: object = None  # the final dual variable, when asked for
 
 
-def _problem(M, L, S, lam, mu, tol, maxit) -> RpcaProblem:
+def _problem(M, L, S, lam, mu, tol, maxit, S0=None, Y0=None, Y=None) -> RpcaProblem:
     m, n = casorati_shape(M)
     p = RpcaProblem()
     p.M, p.m, p.n = M.data_ptr(), m, n
@@ -193,23 +194,34 @@ def _problem(M, L, S, lam, mu, tol, maxit) -> RpcaProblem:
     p.mu = -1.0 if mu is None else float(mu)
     p.tol, p.maxit = float(tol), int(maxit)
     p.L, p.S = L.data_ptr(), S.data_ptr()
+    for name, t in (("S0", S0), ("Y0", Y0)):
+        if t is not None:
+            if t.shape != M.shape or t.stride() != M.stride() or t.dtype != M.dtype or t.device != M.device:
+                raise ValueError(f"{name} must have M's shape, layout, dtype and device")
+            setattr(p, name, t.data_ptr())
+    if Y is not None:
+        p.Y = Y.data_ptr()
     return p
 
 
 def solve(M, lam: Optional[float] = None, mu: Optional[float] = None, tol: float = 1e-7,
-          maxit: int = 500, gram_mode: int = RPCA_GRAM_DEFAULT) -> SolveResult:
-    """One RPCA solve of M; L and S are returned in M's layout.  A negative
-    status raises RuntimeError."""
+          maxit: int = 500, gram_mode: int = RPCA_GRAM_DEFAULT, S0=None, Y0=None,
+          return_Y: bool = False) -> SolveResult:
+    """One RPCA solve of M; L and S are returned in M's layout.  S0, Y0
+    (optional, M's layout) start the iteration from a given S and Y instead
+    of zero; return_Y also returns the final dual Y.  A negative status
+    raises RuntimeError."""
     import torch
     _check_device(M)
     dt = _dtype_code(M)
     L = torch.empty_like(M)
     S = torch.empty_like(M)
-    p = _problem(M, L, S, lam, mu, tol, maxit)
+    Y = torch.empty_like(M) if return_Y else None
+    p = _problem(M, L, S, lam, mu, tol, maxit, S0, Y0, Y)
     rc = rpca_solve_ex(p, dt, gram_mode, _stream_ptr(M))
     if rc < 0:
         raise RuntimeError(f"rpca solve failed: {rpca_strerror(rc)} ({rc}) {rpca_last_error()}")
-    return SolveResult(L, S, int(p.iterations), int(p.status), float(p.residual))
+    return SolveResult(L, S, int(p.iterations), int(p.status), float(p.residual), Y)
 
 
 def solve_many(Ms: Sequence, lam: Optional[float] = None, mu: Optional[float] = None,

@@ -53,6 +53,9 @@ class RpcaProblem(ctypes.Structure):
         ("iterations", ctypes.c_int32),
         ("status", ctypes.c_int32),
         ("residual", ctypes.c_double),
+        ("S0", ctypes.c_void_p),
+        ("Y0", ctypes.c_void_p),
+        ("Y", ctypes.c_void_p),
     ]
 
 

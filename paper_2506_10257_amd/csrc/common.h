@@ -38,7 +38,7 @@ struct SolveState {
   int32_t nonfinite;                // non-finite entries seen by the init pass
   int32_t sweeps;                   // Jacobi sweeps of the last eigensolve
   int32_t sweeps_total;             // over the whole solve
-  int32_t pad;
+  int32_t warm_stage;               // given start: 0 norms pending, 1 Gram of A_1 pending, 2 running
   int64_t trace[8];                 // phase times of the eigensolve (trace builds only)
 };
 
@@ -48,6 +48,9 @@ struct SolveDesc {
   void* Y[2];             // ping-pong Y iterates (m x n)
   void* Lout;             // caller's L
   void* Sout;             // caller's S
+  void* Yout;             // caller's Y (optional, else null)
+  const void* S0;         // caller's starting S (optional; null = zero)
+  const void* Y0;         // caller's starting Y (optional; null = zero)
   double* partials;       // slots x pstride
   double* gpartials;      // groups x pstride
   void* P;                // nb x nb thresholding projector, storage precision
@@ -61,6 +64,7 @@ struct SolveDesc {
   int32_t slots, groups;  // partial slots (= tiles); ceil(slots / kGroup)
   int32_t pstride;        // doubles per partial slot
   int32_t maxit;
+  int32_t warm;           // 1 when the solve starts from a given S0 / Y0
   double lam_in, mu_in, tol;
 };
 

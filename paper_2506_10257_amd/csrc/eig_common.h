@@ -144,10 +144,17 @@ __device__ inline double dot4(F&& term) {
 // non-finite count).  At the first step it records the norms of X and fixes
 // mu and lambda (Sec. II-A); afterwards it applies the stopping test of the
 // pass that just ran, ||X - L - S||_F < tol ||X||_F, and the iteration cap.
-// Returns 1 when the iteration continues.
+// A solve with a given start (S0, Y0) stops after fixing mu (the Gram of its
+// first iterate needs mu) and eigensolves at its next launch.
+// Returns 1 when the eigensolve of this launch goes ahead.
 __device__ inline int control_step(const SolveDesc& d, SolveState* st, const double* scal, int kd) {
   int go = 0;
-  if (kd == 0) {
+  if (kd == 0 && d.warm && st->warm_stage == 1) {
+    // given start: the reduced Gram is that of A_1 = X - S0 + Y0/mu (the
+    // norms and mu were fixed by the previous launch)
+    st->warm_stage = 2;
+    go = 1;
+  } else if (kd == 0) {
     st->nX1 = scal[1];
     st->nXF2 = scal[2];
     st->nonfinite = scal[3] > 0.0 ? 1 : 0;
@@ -170,7 +177,10 @@ __device__ inline int control_step(const SolveDesc& d, SolveState* st, const dou
       st->tau = 1.0 / mu;
       st->lam = lam;
       st->gamma = lam / mu;
-      go = 1;
+      // a given start needs one more pass for the Gram of A_1 before the
+      // first eigensolve
+      st->warm_stage = d.warm ? 1 : 0;
+      go = d.warm ? 0 : 1;
     }
   } else {
     st->r2 = scal[0];

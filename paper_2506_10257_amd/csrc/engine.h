@@ -46,6 +46,10 @@ struct SolveRec {
   const void* M = nullptr;
   void* L = nullptr;
   void* S = nullptr;
+  void* Yout = nullptr;        // optional final Y
+  const void* S0 = nullptr;    // optional starting S
+  const void* Y0 = nullptr;    // optional starting Y
+  int warm = 0;                // starts from S0 / Y0
   int64_t m = 0;
   int32_t n = 0;
   double lam = -1.0, mu = -1.0, tol = 0.0;
@@ -59,9 +63,12 @@ struct SolveRec {
 };
 
 struct LaneRun {
-  std::vector<std::pair<int, std::pair<int, int>>> classes;  // (nb, (item offset, count))
+  std::vector<std::pair<int, std::pair<int, int>>> classes;  // (class key, (item offset, count))
   std::vector<std::pair<int, std::pair<int, int>>> eigs;     // (class, (id offset, count))
   int gitem_off = 0, gitem_cnt = 0;
+  // the same for the lane's solves with a given start (extra init stage)
+  std::vector<std::pair<int, std::pair<int, int>>> warm_classes, warm_eigs;
+  int warm_gitem_off = 0, warm_gitem_cnt = 0;
   std::vector<int> solves;                                   // plan-local solve indices
 };
 

@@ -296,6 +296,27 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
     for (int i : lr.solves)
       for (int g = 0; g < recs[i]->geo.groups; ++g) gitems.push_back(GroupItem{i, g});
     lr.gitem_cnt = static_cast<int>(gitems.size()) - lr.gitem_off;
+    // subsets for the extra init stage of the solves with a given start
+    for (int key : keys) {
+      const int off = static_cast<int>(items.size());
+      for (int i : lr.solves)
+        if (recs[i]->warm && class_key(recs[i]->geo) == key)
+          for (int q = 0; q < recs[i]->geo.slots; ++q) items.push_back(WorkItem{i, q});
+      const int cnt = static_cast<int>(items.size()) - off;
+      if (cnt > 0) lr.warm_classes.push_back({key, {off, cnt}});
+    }
+    for (int cls : {16, 32, 64, kEigWideMaxN}) {
+      const int off = static_cast<int>(ids.size());
+      for (int i : lr.solves)
+        if (recs[i]->warm && eig_class(recs[i]->n) == cls) ids.push_back(i);
+      const int cnt = static_cast<int>(ids.size()) - off;
+      if (cnt > 0) lr.warm_eigs.push_back({cls, {off, cnt}});
+    }
+    lr.warm_gitem_off = static_cast<int>(gitems.size());
+    for (int i : lr.solves)
+      if (recs[i]->warm)
+        for (int g = 0; g < recs[i]->geo.groups; ++g) gitems.push_back(GroupItem{i, g});
+    lr.warm_gitem_cnt = static_cast<int>(gitems.size()) - lr.warm_gitem_off;
   }
 
   const size_t off_desc = 0;
@@ -319,6 +340,10 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
     d.Y[1] = b + r.big.Y1;
     d.Lout = r.L;
     d.Sout = r.S;
+    d.Yout = r.Yout;
+    d.S0 = r.S0;
+    d.Y0 = r.Y0;
+    d.warm = r.warm;
     d.partials = reinterpret_cast<double*>(b + r.big.part);
     d.gpartials = reinterpret_cast<double*>(b + r.big.gpart);
     d.P = b + r.big.P;
@@ -463,6 +488,20 @@ hipError_t enqueue_init(const Plan& plan, const Lanes& L) {
       ev_end(s);
     }
     EQ(launch_reduce(lr.gitem_cnt, s, plan.descs, plan.gitems + lr.gitem_off));
+    // solves with a given start: fix mu, then the Gram of A_1 = X - S0 + Y0/mu
+    for (const auto& er : lr.warm_eigs) {
+      if (er.first == kEigWideMaxN)
+        EQ(launch_eig_wide(plan.dtype == RPCA_F32 ? 1 : 0, er.second.second, s, plan.descs,
+                           plan.ids + er.second.first));
+      else
+        EQ(launch_eig(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s, plan.descs,
+                      plan.ids + er.second.first));
+    }
+    for (const auto& wc : lr.warm_classes)
+      EQ(launch_stream(plan.dtype, wc.first, kModeWarm, wc.second.second, s, plan.descs,
+                       plan.items + wc.second.first));
+    if (lr.warm_gitem_cnt > 0)
+      EQ(launch_reduce(lr.warm_gitem_cnt, s, plan.descs, plan.gitems + lr.warm_gitem_off));
   }
   return hipSuccess;
 }
@@ -537,13 +576,25 @@ int make_rec(const rpca_problem& p, int dtype, int gram_mode, SolveRec& r) {
     return RPCA_ERR_ARG;
   if (!std::isfinite(p.lambda) || !std::isfinite(p.mu) || std::isnan(p.tol)) return RPCA_ERR_ARG;
   const size_t bytes = static_cast<size_t>(p.m) * static_cast<size_t>(p.n) * (dtype == RPCA_F32 ? 4 : 8);
-  if (overlap(p.M, p.L, bytes) || overlap(p.M, p.S, bytes) || overlap(p.L, p.S, bytes))
-    return RPCA_ERR_ARG;
+  // outputs must not overlap each other or any input
+  const void* outs[3] = {p.L, p.S, p.Y};
+  const void* ins[3] = {p.M, p.S0, p.Y0};
+  for (int a = 0; a < 3; ++a) {
+    if (!outs[a]) continue;
+    for (int b = a + 1; b < 3; ++b)
+      if (outs[b] && overlap(outs[a], outs[b], bytes)) return RPCA_ERR_ARG;
+    for (int b = 0; b < 3; ++b)
+      if (ins[b] && overlap(outs[a], ins[b], bytes)) return RPCA_ERR_ARG;
+  }
   if (!geometry(p.m, p.n, dtype, gram_mode, r.geo)) return RPCA_ERR_UNSUPPORTED;
   r.big = big_layout(p.m, p.n, r.geo);
   r.M = p.M;
   r.L = p.L;
   r.S = p.S;
+  r.Yout = p.Y;
+  r.S0 = p.S0;
+  r.Y0 = p.Y0;
+  r.warm = (p.S0 || p.Y0) ? 1 : 0;
   r.m = p.m;
   r.n = static_cast<int32_t>(p.n);
   r.lam = p.lambda;

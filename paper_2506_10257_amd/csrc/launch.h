@@ -10,7 +10,10 @@ namespace rpca {
 constexpr int kClassesF32[] = {4, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 56, 60, 64};
 constexpr int kClassesF64[] = {4, 8, 10, 12, 16, 20, 24, 28, 32};
 
-enum StreamMode { kModeInit = 0, kModeUpdate = 1, kModeFinalize = 2 };
+// kModeWarm: for a solve started from a given S0 / Y0, the Gram of the first
+// iterate A_1 = X - S0 + Y0/mu (after mu is fixed), copying S0 and Y0 into the
+// iterate buffers that the first update pass reads.
+enum StreamMode { kModeInit = 0, kModeUpdate = 1, kModeFinalize = 2, kModeWarm = 3 };
 
 // dtype 0 = FP64, 1 = FP32 (as RPCA_F64 / RPCA_F32).
 hipError_t launch_stream_f32(int nb, int mode, int grid, hipStream_t stream,

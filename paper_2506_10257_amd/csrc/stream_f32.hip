@@ -12,9 +12,11 @@ hipError_t launch_stream_f32(int nb, int mode, int grid, hipStream_t stream,
 #define X(N)                                                                              \
   case N:                                                                                 \
     if (mode == kModeInit)                                                                \
-      hipLaunchKernelGGL((k_stream<float, N, true>), g, b, 0, stream, descs, items);       \
+      hipLaunchKernelGGL((k_stream<float, N, kModeInit>), g, b, 0, stream, descs, items);       \
     else if (mode == kModeUpdate)                                                         \
-      hipLaunchKernelGGL((k_stream<float, N, false>), g, b, 0, stream, descs, items);      \
+      hipLaunchKernelGGL((k_stream<float, N, kModeUpdate>), g, b, 0, stream, descs, items);      \
+    else if (mode == kModeWarm)                                                           \
+      hipLaunchKernelGGL((k_stream<float, N, kModeWarm>), g, b, 0, stream, descs, items);     \
     else                                                                                  \
       hipLaunchKernelGGL((k_finalize<float, N>), g, b, 0, stream, descs, items);           \
     break;

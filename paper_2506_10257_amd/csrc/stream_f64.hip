@@ -12,9 +12,11 @@ hipError_t launch_stream_f64(int nb, int mode, int grid, hipStream_t stream,
 #define X(N)                                                                              \
   case N:                                                                                 \
     if (mode == kModeInit)                                                                \
-      hipLaunchKernelGGL((k_stream<double, N, true>), g, b, 0, stream, descs, items);       \
+      hipLaunchKernelGGL((k_stream<double, N, kModeInit>), g, b, 0, stream, descs, items);       \
     else if (mode == kModeUpdate)                                                         \
-      hipLaunchKernelGGL((k_stream<double, N, false>), g, b, 0, stream, descs, items);      \
+      hipLaunchKernelGGL((k_stream<double, N, kModeUpdate>), g, b, 0, stream, descs, items);      \
+    else if (mode == kModeWarm)                                                           \
+      hipLaunchKernelGGL((k_stream<double, N, kModeWarm>), g, b, 0, stream, descs, items);     \
     else                                                                                  \
       hipLaunchKernelGGL((k_finalize<double, N>), g, b, 0, stream, descs, items);           \
     break;

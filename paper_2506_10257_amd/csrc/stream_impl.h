@@ -6,11 +6,14 @@
 // pixels: each load instruction is one coalesced 256 B (FP32) / 512 B (FP64)
 // segment.  A workgroup processes one tile of kTile rows.
 //
-// k_stream<INIT=true>   : one pass over X.  sum|X|, sum X^2, non-finite count
+// k_stream<MODE=init>   : one pass over X.  sum|X|, sum X^2, non-finite count
 //                         (for mu and the stopping test) and the Gram X^T X,
 //                         which is the Gram of the first iterate because S and
 //                         Y start at zero.
-// k_stream<INIT=false>  : one ALM iteration k for every row, fused:
+// k_stream<MODE=warm>   : for a solve started from S0, Y0: the Gram of
+//                         A_1 = X - S0 + Y0/mu, copying S0 and Y0 into the
+//                         buffers the first update pass reads.
+// k_stream<MODE=update> : one ALM iteration k for every row, fused:
 //                           a  = x - s + y/mu                  (argument of Eq. 4)
 //                           l  = a P      P = V diag(w) V^T  (Eq. 4 rebuild)
 //                           t  = x - l + y/mu
@@ -54,9 +57,11 @@ __device__ inline double clamp_sym(double v, double g) { return fmin(fmax(v, -g)
 __device__ inline bool finite_val(float v) { return __builtin_isfinite(v); }
 __device__ inline bool finite_val(double v) { return __builtin_isfinite(v); }
 
-template <typename T, int NB, bool INIT>
+template <typename T, int NB, int MODE>
 __global__ void __launch_bounds__(kThreads)
 k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
+  constexpr bool INIT = MODE == 0;  // kModeInit
+  constexpr bool WARM = MODE == 3;  // kModeWarm
   constexpr int NB4 = (NB + 3) / 4 * 4;
   constexpr int LDT = kTile + 1;  // odd row stride: frames of one row fall in different banks
   constexpr size_t kTileBytes = sizeof(T) * NB4 * LDT;
@@ -73,7 +78,9 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   const SolveDesc& d = descs[wi.solve];
   SolveState* st = d.st;
   int k = 0;
-  if constexpr (!INIT) {
+  if constexpr (WARM) {
+    if (st->done || st->warm_stage != 1) return;
+  } else if constexpr (!INIT) {
     if (st->done) return;
     k = st->iter;
   }
@@ -85,7 +92,8 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   const gptr<T> Sout = as_global<T>(d.S[k & 1]);
   const gptr<T> Yout = as_global<T>(d.Y[k & 1]);
   const cptr<T> P = as_const<T>(d.P);
-  const bool first = (k == 1);
+  // S_0 = Y_0 = 0 are not read unless the solve starts from a given S0 / Y0
+  const bool first = (k == 1) && !d.warm;
   T mu = 0, imu = 0, gam = 0;
   if constexpr (!INIT) {
     mu = static_cast<T>(st->mu);
@@ -121,6 +129,26 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
         s2 = fma(xd, xd, s2);
         nf += finite_val(x) ? 0.0 : 1.0;
         tileA[j * LDT + tid] = x;
+      }
+    } else if constexpr (WARM) {
+      // A_1 = X - S0 + Y0/mu; S0 and Y0 go to the buffers pass 1 reads
+      const gptr<const T> S0 = as_global<T>(d.S0);
+      const gptr<const T> Y0 = as_global<T>(d.Y0);
+      const gptr<T> S1 = as_global<T>(d.S[0]);
+      const gptr<T> Y1 = as_global<T>(d.Y[0]);
+#pragma unroll
+      for (int j = 0; j < NB4; ++j) {
+        T a = 0;
+        if (j < n && valid) {
+          const size_t col = static_cast<size_t>(j) * m;
+          const T x = (X + col)[p];
+          const T s = d.S0 ? (S0 + col)[p] : T(0);
+          const T y = d.Y0 ? (Y0 + col)[p] : T(0);
+          (S1 + col)[p] = s;
+          (Y1 + col)[p] = y;
+          a = fma(y, imu, x - s);
+        }
+        tileA[j * LDT + tid] = a;
       }
     } else {
       T x[NB], y[NB], a[NB];
@@ -250,16 +278,19 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
   const cptr<T> P = as_const<T>(d.P);
   const gptr<T> L = as_global<T>(d.Lout);
   const gptr<T> So = as_global<T>(d.Sout);
-  const bool first = (k == 1);
+  const gptr<T> Yo = as_global<T>(d.Yout);
+  const gptr<const T> Yk = as_global<T>(static_cast<const void*>(d.Y[k & 1]));
+  const bool first = (k == 1) && !d.warm;
   const T imu = static_cast<T>(st->imu);
   {
     const uint32_t p = static_cast<uint32_t>(wi.slot) * kTile + tid;
     if (p >= m) return;
-    if (k == 0) {  // sum|X| == 0: L = S = 0
+    if (k == 0) {  // sum|X| == 0: L = S = 0 (and Y = 0)
       for (int j = 0; j < n; ++j) {
         const size_t col = static_cast<size_t>(j) * m;
         (L + col)[p] = T(0);
         (So + col)[p] = T(0);
+        if (d.Yout) (Yo + col)[p] = T(0);
       }
       return;
     }
@@ -287,6 +318,7 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
         const size_t col = static_cast<size_t>(j) * m;
         (L + col)[p] = l;
         (So + col)[p] = (Sk + col)[p];
+        if (d.Yout) (Yo + col)[p] = (Yk + col)[p];
       }
     }
   }

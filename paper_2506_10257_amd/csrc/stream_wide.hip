@@ -116,9 +116,11 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   constexpr int NGT = NT16 * (NT16 + 1) / 2;            // Gram output blocks (upper)
   constexpr int MG = (NGT + NW - 1) / NW;               // ... per wave
   constexpr bool INIT = PHASE == kModeInit;
+  constexpr bool WARM = PHASE == kModeWarm;
   constexpr bool FIN = PHASE == kModeFinalize;
+  constexpr bool REB = !INIT && !WARM;  // passes that rebuild L
   __shared__ float At[NBK * LDA];
-  __shared__ float Lt[INIT ? 1 : NB * LDA];
+  __shared__ float Lt[REB ? NB * LDA : 1];
   __shared__ double wred[NW][kScalars];
 
   const int tid = threadIdx.x;
@@ -127,6 +129,9 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   const SolveDesc& d = descs[wi.solve];
   SolveState* st = d.st;
   int k = 0;
+  if constexpr (WARM) {
+    if (st->done || st->warm_stage != 1) return;
+  }
   if constexpr (PHASE == kModeUpdate) {
     if (st->done) return;
     k = st->iter;
@@ -143,7 +148,8 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   const gptr<const float> Yin = as_global<float>(static_cast<const void*>(d.Y[(k + 1) & 1]));
   const gptr<float> Sout = as_global<float>(d.S[k & 1]);
   const gptr<float> Yout = as_global<float>(d.Y[k & 1]);
-  const bool first = (k == 1);
+  // S_0 = Y_0 = 0 are not read unless the solve starts from a given S0 / Y0
+  const bool first = (k == 1) && !d.warm;
   float mu = 0.f, imu = 0.f, gam = 0.f;
   if constexpr (!INIT) {
     mu = static_cast<float>(st->mu);
@@ -162,7 +168,7 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   float pa[PREC ? 1 : NOWN][PREC ? 1 : NK4];
   bf8 ph[PREC ? NOWN : 1][PREC ? NKB : 1], pl[PREC ? NOWN : 1][PREC ? NKB : 1];
   bf8 pm[X6 ? NOWN : 1][X6 ? NKB : 1];
-  if constexpr (!INIT) {
+  if constexpr (REB) {
     const gptr<const float> P = as_global<float>(static_cast<const void*>(d.P));
 #pragma unroll
     for (int o = 0; o < NOWN; ++o) {
@@ -218,13 +224,17 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
           const size_t off = static_cast<size_t>(j) * static_cast<size_t>(m) + static_cast<size_t>(p);
           as_global<float>(d.Lout)[off] = 0.f;
           as_global<float>(d.Sout)[off] = 0.f;
+          if (d.Yout) as_global<float>(d.Yout)[off] = 0.f;
         }
       }
       return;
     }
   }
-  // Raw loads of one tile: X, and S_{k-1}, Y_{k-1} after the first iteration.
-  const bool read_sy = !INIT && k >= 1 && !first;
+  // Raw loads of one tile: X, and S_{k-1}, Y_{k-1} after the first iteration
+  // (the given S0, Y0 in the warm pass).
+  const bool read_sy = REB && k >= 1 && !first;
+  const gptr<const float> S0 = as_global<float>(d.S0);
+  const gptr<const float> Y0 = as_global<float>(d.Y0);
   auto load_tile = [&](int tile, float* xr, float* sr, float* yr) {
     const int64_t p = static_cast<int64_t>(tile) * R + l;
 #pragma unroll
@@ -236,7 +246,10 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
       if (j < n && p < m) {
         const size_t off = static_cast<size_t>(j) * static_cast<size_t>(m) + static_cast<size_t>(p);
         xr[q] = X[off];
-        if (read_sy) {
+        if constexpr (WARM) {
+          if (d.S0) sr[q] = S0[off];
+          if (d.Y0) yr[q] = Y0[off];
+        } else if (read_sy) {
           sr[q] = Sin[off];
           yr[q] = Yin[off];
         }
@@ -278,6 +291,11 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
           a = x[q];
         } else {
           a = fmaf(y[q], imu, x[q] - sv[q]);
+          if constexpr (WARM) {  // the buffers the first update pass reads
+            const size_t off = static_cast<size_t>(j) * static_cast<size_t>(m) + static_cast<size_t>(p);
+            as_global<float>(d.S[0])[off] = sv[q];
+            as_global<float>(d.Y[0])[off] = y[q];
+          }
         }
       }
       At[j * LDA + l] = a;
@@ -287,7 +305,7 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
     }
     __syncthreads();
 
-    if constexpr (!INIT) {
+    if constexpr (REB) {
       // 2. rebuild L^T = P A^T into Lt
 #pragma unroll
       for (int o = 0; o < NOWN; ++o) {
@@ -337,6 +355,8 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
           if constexpr (FIN) {
             as_global<float>(d.Lout)[off] = lv;
             as_global<float>(d.Sout)[off] = as_global<float>(static_cast<const void*>(d.S[k & 1]))[off];
+            if (d.Yout)
+              as_global<float>(d.Yout)[off] = as_global<float>(static_cast<const void*>(d.Y[k & 1]))[off];
           } else {
             const float tt = fmaf(y[q], imu, x[q]) - lv;            // X - L + Y/mu
             const float sn = tt - fminf(fmaxf(tt, -gam), gam);      // Eq. 5 shrink
@@ -441,6 +461,8 @@ hipError_t launch_wide(int nb, int mode, int prec, int grid, hipStream_t stream,
   if (nb == N && prec == P) {                                                                  \
     if (mode == kModeInit)                                                                     \
       hipLaunchKernelGGL((k_wide<N, kModeInit, P>), g, b, 0, stream, descs, items);            \
+    else if (mode == kModeWarm)                                                                \
+      hipLaunchKernelGGL((k_wide<N, kModeWarm, P>), g, b, 0, stream, descs, items);            \
     else if (mode == kModeUpdate)                                                              \
       hipLaunchKernelGGL((k_wide<N, kModeUpdate, P>), g, b, 0, stream, descs, items);          \
     else                                                                                       \

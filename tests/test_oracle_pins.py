@@ -343,3 +343,58 @@ def test_permutation_equivariance(small_us):
     assert a.iterations == b.iterations
     assert rel_fro(b.L, a.L[pr][:, pc]) <= 1e-11
     assert rel_fro(b.S, a.S[pr][:, pc]) <= 1e-11
+
+
+# ------------------------------------------------ iteration from a given start
+def test_explicit_zero_start_is_the_default():
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((30, 6))
+    a = rpca(X, tol=1e-8, maxit=200)
+    b = rpca(X, tol=1e-8, maxit=200, S0=np.zeros_like(X), Y0=np.zeros_like(X))
+    assert a.iterations == b.iterations
+    assert np.array_equal(a.L, b.L) and np.array_equal(a.S, b.S) and np.array_equal(a.Y, b.Y)
+
+
+def test_dual_bound_holds_after_one_step_from_any_start():
+    """|Y_1| <= lam whatever S0, Y0 (Eq. 5 makes X - L + Y/mu - S_1 a clamp
+    to [-lam/mu, lam/mu], and Eq. 6 scales it by mu)."""
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((25, 7))
+    S0 = 5.0 * rng.standard_normal(X.shape)
+    Y0 = 10.0 * rng.standard_normal(X.shape)
+    r = rpca(X, tol=0.0, maxit=1, S0=S0, Y0=Y0)
+    assert np.max(np.abs(r.Y)) <= r.lam * (1 + 1e-12)
+
+
+def test_converged_point_is_a_fixed_point_of_the_iteration():
+    """Started from its own converged (S, Y), a solve stops after one step
+    with the same decomposition."""
+    L0, S0_ = planted_low_rank_sparse(120, 30, 3, 0.05, 13)
+    X = L0 + S0_
+    ref = rpca(X, tol=1e-12, maxit=5000)
+    assert ref.status == 0
+    r = rpca(X, tol=1e-9, maxit=50, S0=ref.S, Y0=ref.Y)
+    assert r.iterations == 1
+    assert np.linalg.norm(r.L - ref.L) <= 1e-9 * np.linalg.norm(ref.L)
+    assert np.linalg.norm(r.S - ref.S) <= 1e-9 * np.linalg.norm(ref.S)
+
+
+def test_warm_start_from_shifted_window_needs_fewer_iterations():
+    """Sliding windows (the real-time use of the method): starting a window
+    from the previous window's S and Y, shifted by the step, is a valid start
+    of the same iteration and reaches the same tolerance in fewer steps."""
+    from synth import make_window
+    w = make_window(32, 32, 25, 2, 4, 3, 20.0, 14)
+    X = w.X()
+    prev = rpca(X[:, :20], tol=1e-6, maxit=2000)
+    cur_cold = rpca(X[:, 5:25], tol=1e-6, maxit=2000)
+    S0 = np.zeros((X.shape[0], 20))
+    Y0 = np.zeros((X.shape[0], 20))
+    S0[:, :15] = prev.S[:, 5:]
+    Y0[:, :15] = prev.Y[:, 5:]
+    cur_warm = rpca(X[:, 5:25], tol=1e-6, maxit=2000, S0=S0, Y0=Y0)
+    assert cur_warm.status == 0 and cur_cold.status == 0
+    assert cur_warm.iterations < cur_cold.iterations
+    # both are tol-accurate solutions of the same problem
+    rel = np.linalg.norm(cur_warm.L - cur_cold.L) / np.linalg.norm(cur_cold.L)
+    assert rel < 1e-3
