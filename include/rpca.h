@@ -295,6 +295,51 @@ int rpca_autotune(int32_t dtype, int64_t rows, void* stream);
 int rpca_autotune_save(const char* path);
 int rpca_autotune_load(const char* path);
 
+/*
+ * ---- steps around the solve, on the device ------------------------------
+ *
+ * All arrays are device arrays of the given dtype (RPCA_F32 / RPCA_F64) in
+ * the Casorati layout; host outputs are written after the work completed.
+ * Sums are FP64 and fixed-order (no atomics).
+ *
+ * rpca_frame_correlation: rho[t] (host, n-1 doubles) = Pearson correlation
+ *   of frames t and t+1 over the m pixels.  2 <= n <= 160, m >= 2.  A frame
+ *   with zero variance gives correlation 0.
+ * rpca_frame_keep: host helper.  keep[t] = 1 when frame t correlates at
+ *   least `threshold` with one of its neighbours (max of rho[t-1], rho[t]
+ *   where they exist), else 0; returns the number kept.  The paper's in vivo
+ *   reference drops frames that correlate below 0.8 with their neighbours
+ *   (Sec. III); "with one of its neighbours" is this library's reading: a
+ *   single jumping frame is dropped, its neighbours are kept.
+ * rpca_frame_select: copies the kept frames of M (keep[t] != 0, host) in
+ *   order into out (device, m x kept), stream-ordered; returns the count.
+ * rpca_moving_average: out[:, t] = mean of M[:, t .. t+W-1] for t = 0 ..
+ *   n-W (the paper's temporal moving average over 20 frames, Sec. III);
+ *   out is m x (n-W+1).  1 <= W <= 32, W <= n.  Running FP64 sum.
+ * rpca_dice: binarises A >= thr_a and B >= thr_b (compared in FP64) over
+ *   `count` entries; counts[3] (host, optional) = |both|, |A|, |B|;
+ *   *dice (host, optional) = 2|both| / (|A| + |B|) (Eq. 8; 1 if both empty).
+ * rpca_rmse: *out = sqrt(mean((A - B)^2)) over `count` entries (Eq. 7).
+ * rpca_masked_mean: *out = mean of A over entries with mask != 0 (uint8
+ *   device mask): the binarisation threshold of Sec. II-F (the mean
+ *   intensity at the bubble locations).  RPCA_ERR_ARG if the mask is empty.
+ * Each returns RPCA_OK (or the count), RPCA_ERR_ARG, RPCA_ERR_NOMEM or
+ * RPCA_ERR_DEVICE.
+ */
+int rpca_frame_correlation(const void* M, int64_t m, int64_t n, int32_t dtype, double* rho,
+                           void* stream);
+int rpca_frame_keep(const double* rho, int64_t n, double threshold, int32_t* keep);
+int rpca_frame_select(const void* M, int64_t m, int64_t n, int32_t dtype, const int32_t* keep,
+                      void* out, void* stream);
+int rpca_moving_average(const void* M, int64_t m, int64_t n, int32_t W, int32_t dtype, void* out,
+                        void* stream);
+int rpca_dice(const void* A, double thr_a, const void* B, double thr_b, int64_t count,
+              int32_t dtype, int64_t* counts, double* dice, void* stream);
+int rpca_rmse(const void* A, const void* B, int64_t count, int32_t dtype, double* out,
+              void* stream);
+int rpca_masked_mean(const void* A, const uint8_t* mask, int64_t count, int32_t dtype,
+                     double* out, void* stream);
+
 /* Static description of a status code. */
 const char* rpca_strerror(int code);
 

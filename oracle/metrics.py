@@ -51,3 +51,50 @@ def rel_fro(est: np.ndarray, ref: np.ndarray) -> float:
     if den == 0.0:
         return 0.0 if num == 0.0 else float("inf")
     return num / den
+
+
+# --------------------------------------------------- steps around the solve
+def frame_correlations(X: np.ndarray) -> np.ndarray:
+    """Pearson correlation of consecutive frames (columns) t, t+1 of the
+    Casorati matrix X (m x n), t = 0 .. n-2; a frame with zero variance gives
+    0.  Used to drop frames that correlate poorly with their neighbours
+    (the paper's in vivo reference, Sec. III)."""
+    X = np.asarray(X, dtype=np.float64)
+    out = np.zeros(X.shape[1] - 1)
+    for t in range(X.shape[1] - 1):
+        a = X[:, t] - X[:, t].mean()
+        b = X[:, t + 1] - X[:, t + 1].mean()
+        den = np.sqrt(np.dot(a, a) * np.dot(b, b))
+        out[t] = np.dot(a, b) / den if den > 0 else 0.0
+    return out
+
+
+def frame_keep(rho: np.ndarray, threshold: float = 0.8) -> np.ndarray:
+    """Reading of the frame rejection: frame t is kept when it correlates at
+    least `threshold` with one of its neighbours (the larger of rho[t-1] and
+    rho[t] where they exist)."""
+    n = len(rho) + 1
+    keep = np.zeros(n, dtype=bool)
+    for t in range(n):
+        nb = []
+        if t > 0:
+            nb.append(rho[t - 1])
+        if t + 1 < n:
+            nb.append(rho[t])
+        keep[t] = (not nb) or max(nb) >= threshold
+    return keep
+
+
+def moving_average(X: np.ndarray, W: int) -> np.ndarray:
+    """Temporal moving average over W frames, 'valid' part: column t is the
+    mean of columns t .. t+W-1 (Sec. III, 20-frame window)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[1]
+    return np.stack([X[:, t:t + W].mean(axis=1) for t in range(n - W + 1)], axis=1)
+
+
+def masked_mean(A: np.ndarray, mask: np.ndarray) -> float:
+    """Mean of A over the entries where mask is set (binarisation threshold,
+    Sec. II-F)."""
+    A = np.asarray(A, dtype=np.float64)
+    return float(A[np.asarray(mask, dtype=bool)].mean())

@@ -36,6 +36,8 @@ EXPORTS = (
     "rpca_server_create", "rpca_server_submit", "rpca_server_step", "rpca_server_pending",
     "rpca_server_peak_bytes", "rpca_server_request_bytes", "rpca_server_destroy",
     "rpca_autotune", "rpca_autotune_save", "rpca_autotune_load",
+    "rpca_frame_correlation", "rpca_frame_keep", "rpca_frame_select", "rpca_moving_average",
+    "rpca_dice", "rpca_rmse", "rpca_masked_mean",
 )
 
 
@@ -148,5 +150,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpca_autotune_save.restype = ctypes.c_int
     lib.rpca_autotune_load.argtypes = [ctypes.c_char_p]
     lib.rpca_autotune_load.restype = ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    lib.rpca_frame_correlation.argtypes = [vp, i64, i64, i32, dp, vp]
+    lib.rpca_frame_keep.argtypes = [dp, i64, dbl, ip]
+    lib.rpca_frame_select.argtypes = [vp, i64, i64, i32, ip, vp, vp]
+    lib.rpca_moving_average.argtypes = [vp, i64, i64, i32, i32, vp, vp]
+    lib.rpca_dice.argtypes = [vp, dbl, vp, dbl, i64, i32, lp, dp, vp]
+    lib.rpca_rmse.argtypes = [vp, vp, i64, i32, dp, vp]
+    lib.rpca_masked_mean.argtypes = [vp, vp, i64, i32, dp, vp]
+    for name in ("rpca_frame_correlation", "rpca_frame_keep", "rpca_frame_select",
+                 "rpca_moving_average", "rpca_dice", "rpca_rmse", "rpca_masked_mean"):
+        getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
