@@ -10,8 +10,9 @@ value = sum over timed steps of m * n * iterations / wall time of the steps.
 
 The JSON line also carries
   roofline     : the fused update kernel's algorithmic bytes per launch over
-                 its mean launch time (a HIP event pair per launch on the
-                 library's stream, over a repeat of the timed steps) against
+                 its mean launch time (a HIP start/stop event pair that each
+                 launch records on its own stream from its dispatch packet,
+                 over a repeat of the timed steps) against
                  the 8 TB/s HBM peak, and the HBM bytes per launch measured
                  with rocprofv3 counters (profiles/);
   cpu_baseline : the FP64 CPU oracle timed on a bounded number of iterations
@@ -137,7 +138,7 @@ def run_batch(args):
     iters = [r.iterations for r in res]
 
     # One more step with kernel timing: the library then runs every solve on
-    # one stream with direct launches and a HIP event pair per launch.
+    # one stream with direct launches, each recording a HIP start/stop event pair.
     rp.rpca_profile_read(reset=True)
     rp.rpca_profile_enable(True)
     t0 = time.perf_counter()
@@ -586,9 +587,10 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
 
-    # Kernel timing: the same steps again with a HIP event pair around every
-    # launch on the launching stream (direct launches, since per-launch
-    # events cannot be read back from a replayed graph chunk).
+    # Kernel timing: the same steps again, every launch recording a HIP
+    # start/stop event pair of its own on the launching stream (direct
+    # launches, since per-launch events cannot be read back from a replayed
+    # graph chunk).
     rp.rpca_profile_read(reset=True)
     rp.rpca_profile_enable(True)
     ktimes = []

@@ -158,8 +158,10 @@ int rpca_solve_ex(rpca_problem* prob, int32_t dtype, int32_t gram_mode, void* st
 size_t rpca_footprint_bytes(int64_t m, int64_t n, int32_t dtype);
 
 /*
- * Kernel timing (for measurement).  While enabled, every launch is bracketed
- * by HIP events on the call's stream and the durations are accumulated:
+ * Kernel timing (for measurement).  While enabled, solves run on one stream
+ * with direct launches (no graphs); each solve-path launch records a HIP
+ * start/stop event pair from its own dispatch packet (hipExtLaunchKernel), so
+ * a duration covers the kernel alone, and the durations are accumulated:
  * init pass, eigensolve launches and update-pass launches that did work, and
  * the finalize pass.  update_bytes is the algorithmic traffic of the timed
  * update passes: 5 words per matrix entry (read X, S, Y; write S, Y), 3 on

@@ -358,9 +358,9 @@ hipError_t launch_eig(int dtype, int ncls, int grid, hipStream_t stream, const S
 #define RPCA_EIG_CASE(N, NT)                                                  \
   if (ncls == N && nt == NT) {                                                \
     if (dtype == 0)                                                           \
-      hipLaunchKernelGGL((k_eig<double, N, NT>), g, b, 0, stream, descs, ids); \
+      RPCA_LAUNCH((k_eig<double, N, NT>), g, b, 0, stream, descs, ids); \
     else                                                                      \
-      hipLaunchKernelGGL((k_eig<float, N, NT>), g, b, 0, stream, descs, ids);  \
+      RPCA_LAUNCH((k_eig<float, N, NT>), g, b, 0, stream, descs, ids);  \
     return hipGetLastError();                                                 \
   }
   RPCA_EIG_CASE(16, 256)

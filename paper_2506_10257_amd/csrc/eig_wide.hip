@@ -316,9 +316,9 @@ hipError_t launch_eig_wide(int dtype, int grid, hipStream_t stream, const SolveD
   if (grid <= 0) return hipSuccess;
   const dim3 g(grid), b(kEigWideThreads);
   if (dtype == 0)
-    hipLaunchKernelGGL((k_eig_wide<double, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+    RPCA_LAUNCH((k_eig_wide<double, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
   else
-    hipLaunchKernelGGL((k_eig_wide<float, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+    RPCA_LAUNCH((k_eig_wide<float, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
   return hipGetLastError();
 }
 

@@ -37,6 +37,8 @@
 
 namespace rpca {
 
+thread_local LaunchEvents t_launch_events;
+
 namespace {
 
 constexpr int kGraphChunk = 16;
@@ -79,13 +81,18 @@ void ev_begin(hipStream_t s, int kind, int iter, int lane, int cls) {
   e.iter = iter;
   e.lane = lane;
   e.cls = cls;
-  (void)hipEventCreate(&e.a);
-  (void)hipEventCreate(&e.b);
-  (void)hipEventRecord(e.a, s);
+  (void)s;
+  // timing-only events: no system-scope fence (the run synchronises its
+  // stream before the pairs are read), so no cache writeback is timed
+  (void)hipEventCreateWithFlags(&e.a, hipEventDisableSystemFence);
+  (void)hipEventCreateWithFlags(&e.b, hipEventDisableSystemFence);
   t_evs->push_back(e);
+  t_launch_events.start = e.a;  // the next launch times itself into the pair
+  t_launch_events.stop = e.b;
 }
 void ev_end(hipStream_t s) {
-  if (t_evs) (void)hipEventRecord(t_evs->back().b, s);
+  (void)s;
+  t_launch_events = LaunchEvents{};
 }
 
 }  // namespace
@@ -844,6 +851,7 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
 
 done:
   t_evs = nullptr;
+  t_launch_events = LaunchEvents{};
   for (auto& e : evs) {
     if (e.a) (void)hipEventDestroy(e.a);
     if (e.b) (void)hipEventDestroy(e.b);

@@ -1,9 +1,29 @@
 // Host-side launchers of the device kernels (internal to the library).
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace rpca {
+
+// Kernel timing: while `start` is set, a solve-path launch on this thread
+// records its own start and end timestamps into the pair (the dispatch packet
+// carries them, so queue time between launches is not counted).  Null when
+// timing is off: then the launch is a plain one.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents t_launch_events;
+
+#define RPCA_LAUNCH(K, G, B, SH, S, ...)                                                      \
+  do {                                                                                       \
+    if (::rpca::t_launch_events.start)                                                       \
+      hipExtLaunchKernelGGL(K, G, B, SH, S, ::rpca::t_launch_events.start,                   \
+                            ::rpca::t_launch_events.stop, 0, __VA_ARGS__);                   \
+    else                                                                                     \
+      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                       \
+  } while (0)
 
 // Frame classes compiled for the register-resident streaming kernels.  A solve
 // with n frames runs on the smallest class >= n.

@@ -12,13 +12,13 @@ hipError_t launch_stream_f64(int nb, int mode, int grid, hipStream_t stream,
 #define X(N)                                                                              \
   case N:                                                                                 \
     if (mode == kModeInit)                                                                \
-      hipLaunchKernelGGL((k_stream<double, N, kModeInit>), g, b, 0, stream, descs, items);       \
+      RPCA_LAUNCH((k_stream<double, N, kModeInit>), g, b, 0, stream, descs, items);       \
     else if (mode == kModeUpdate)                                                         \
-      hipLaunchKernelGGL((k_stream<double, N, kModeUpdate>), g, b, 0, stream, descs, items);      \
+      RPCA_LAUNCH((k_stream<double, N, kModeUpdate>), g, b, 0, stream, descs, items);      \
     else if (mode == kModeWarm)                                                           \
-      hipLaunchKernelGGL((k_stream<double, N, kModeWarm>), g, b, 0, stream, descs, items);     \
+      RPCA_LAUNCH((k_stream<double, N, kModeWarm>), g, b, 0, stream, descs, items);     \
     else                                                                                  \
-      hipLaunchKernelGGL((k_finalize<double, N>), g, b, 0, stream, descs, items);           \
+      RPCA_LAUNCH((k_finalize<double, N>), g, b, 0, stream, descs, items);           \
     break;
     X(4) X(8) X(10) X(12) X(16) X(20) X(24) X(28) X(32)
 #undef X

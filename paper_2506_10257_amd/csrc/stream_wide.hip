@@ -460,13 +460,13 @@ hipError_t launch_wide(int nb, int mode, int prec, int grid, hipStream_t stream,
 #define RPCA_WIDE(N, P)                                                                        \
   if (nb == N && prec == P) {                                                                  \
     if (mode == kModeInit)                                                                     \
-      hipLaunchKernelGGL((k_wide<N, kModeInit, P>), g, b, 0, stream, descs, items);            \
+      RPCA_LAUNCH((k_wide<N, kModeInit, P>), g, b, 0, stream, descs, items);            \
     else if (mode == kModeWarm)                                                                \
-      hipLaunchKernelGGL((k_wide<N, kModeWarm, P>), g, b, 0, stream, descs, items);            \
+      RPCA_LAUNCH((k_wide<N, kModeWarm, P>), g, b, 0, stream, descs, items);            \
     else if (mode == kModeUpdate)                                                              \
-      hipLaunchKernelGGL((k_wide<N, kModeUpdate, P>), g, b, 0, stream, descs, items);          \
+      RPCA_LAUNCH((k_wide<N, kModeUpdate, P>), g, b, 0, stream, descs, items);          \
     else                                                                                       \
-      hipLaunchKernelGGL((k_wide<N, kModeFinalize, P>), g, b, 0, stream, descs, items);        \
+      RPCA_LAUNCH((k_wide<N, kModeFinalize, P>), g, b, 0, stream, descs, items);        \
     return hipGetLastError();                                                                  \
   }
   RPCA_WIDE(16, 0) RPCA_WIDE(32, 0) RPCA_WIDE(48, 0) RPCA_WIDE(64, 0)
