@@ -176,9 +176,12 @@ def run_batch(args):
                        "p99": float(np.percentile(walls, 99)) * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_stream<float,NB,false> (all frame classes)",
+                     "kernel": "update pass, all frame classes (k_wide MFMA tile kernel for the "
+                               "classes in tuning.tile_kernel_classes, k_stream register kernel "
+                               "for the others)",
                      "launches": prof["update_launches"],
-                     "measured_on": "one extra step with per-launch HIP events (one stream)"},
+                     "measured_on": "one extra step, each launch recording its own HIP "
+                                    "start/stop event pair (one stream)"},
         "tuning": tuning_summary(),
         "kernel_timed_step": {"ms": timed_wall * 1e3,
                               **{k: prof[k] for k in ("init_ms", "eig_ms", "update_ms", "finalize_ms")}},
@@ -606,7 +609,15 @@ def main():
     upd_ms = prof["update_ms"] / max(prof["update_launches"], 1)
     bytes_per_launch = prof["update_bytes"] / max(prof["update_launches"], 1)
     achieved = bytes_per_launch / (upd_ms * 1e-3) / 1e9 if upd_ms > 0 else 0.0
-    traffic = measured_traffic()
+    # Which update kernel ran: the register kernel of the 20-frame class, or
+    # the MFMA tile kernel (32-frame tile) when the tuner chose it for that
+    # class.  The committed counter summary covers the register kernel only.
+    tiled = args.dtype == "f32" and 20 in tuning_summary()["tile_kernel_classes"]
+    if tiled:
+        kname, traffic = "k_wide<32,kModeUpdate,fp32>", None
+    else:
+        kname = f"k_stream<{'float' if args.dtype == 'f32' else 'double'},20,kModeUpdate>"
+        traffic = measured_traffic() if args.dtype == "f32" else None
     lat = np.array(times) * 1e3
     out = {
         "metric": METRIC,
@@ -628,10 +639,11 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_stream<{'float' if args.dtype == 'f32' else 'double'},20,false>",
+                     "kernel": kname,
                      "bytes_per_launch": bytes_per_launch, "mean_launch_us": upd_ms * 1e3,
                      "launches": prof["update_launches"],
-                     "measured_on": "the same steps repeated with a HIP event pair per launch"},
+                     "measured_on": "the same steps repeated, each launch recording its own HIP "
+                                    "start/stop event pair"},
         "phase_ms_per_solve": {k: prof[k] / max(prof["solves"], 1)
                                for k in ("init_ms", "eig_ms", "update_ms", "finalize_ms")},
         "tuning": tuning_summary(),
