@@ -74,9 +74,11 @@ extern "C" {
                                 order >= 2^-16 (hi*hi, hi*mid, mid*hi, hi*lo,
                                 mid*mid, lo*hi): about FP32 accuracy          */
 
-#define RPCA_N_MAX 112   /* largest frame count n accepted (the FP64 eigensolve
-                            of the n x n Gram keeps G and V in 160 KB of LDS);
-                            RPCA_F64 solves accept n <= 32                   */
+#define RPCA_N_MAX 144   /* largest frame count n accepted by RPCA_F32 solves
+                            (the FP64 eigensolve of the n x n Gram keeps the
+                            packed G in the 160 KB of LDS; above 112 frames
+                            V stays in device memory); RPCA_F64 solves accept
+                            n <= 32                                         */
 
 /*
  * rpca_solve_f64 / rpca_solve_f32 - one RPCA solve.

@@ -14,7 +14,8 @@ constexpr int kThreads = 256;      // threads per streaming workgroup
 constexpr int kTile = 256;         // pixel rows per tile: one row per thread
 constexpr int kGroup = 32;         // partial slots per first-level reduction group
 constexpr int kEigMaxN = 64;       // frame count handled by the double-buffered eigensolver
-constexpr int kEigWideMaxN = 112;  // frame count handled by the in-place eigensolver
+constexpr int kEigWideMaxN = 112;  // frame count handled by the in-place eigensolver (V in LDS)
+constexpr int kEigHugeMaxN = 144;  // ... and by its variant with V in global memory
 constexpr int kEigWideThreads = 1024;
 constexpr int kWideRows = 64;      // pixel rows per tile of the MFMA streaming kernel
 constexpr int kScalars = 4;        // scalar slots at the head of each partial
@@ -55,7 +56,7 @@ struct SolveDesc {
   double* gpartials;      // groups x pstride
   void* P;                // nb x nb thresholding projector, storage precision
   double* V;              // nb x nb eigenvectors of the last eigensolve
-  double* escratch;       // kEigWideMaxN^2 doubles for the wide eigensolver (else null)
+  double* escratch;       // class^2 doubles (112^2 or 144^2) for the wide eigensolver (else null)
   SolveState* st;
   int64_t* wgtrace;       // per-slot timestamps (trace builds only, else null)
   int64_t m;

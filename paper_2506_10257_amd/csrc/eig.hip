@@ -324,7 +324,8 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
 }  // namespace
 
 int eig_class(int n) {
-  return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= kEigMaxN ? 64 : (n <= kEigWideMaxN ? kEigWideMaxN : 0)));
+  if (n <= kEigMaxN) return n <= 16 ? 16 : (n <= 32 ? 32 : 64);
+  return n <= kEigWideMaxN ? kEigWideMaxN : (n <= kEigHugeMaxN ? kEigHugeMaxN : 0);
 }
 
 namespace {

@@ -1,6 +1,6 @@
 // FP64 eigensolve and singular value thresholding weights for windows of 65
-// to 112 frames (paper Sec. II-A, Eq. 4; the paper's own reference uses up to
-// 132 frames, Sec. III-D).
+// to 144 frames (paper Sec. II-A, Eq. 4; the paper's own reference windows
+// have 132 frames).
 //
 // Same method as the LDS eigensolver of the smaller classes: cyclic
 // two-sided Jacobi on the n x n Gram G = A^T A with the round-robin parallel
@@ -13,7 +13,11 @@
 //     J^T G J depends only on block (k1, k2) of G, so each thread owns whole
 //     blocks and overwrites them;
 //   * V is kept in full; row i of V J depends only on row i, so each thread
-//     owns (row, pair) items and overwrites V[i][p], V[i][q];
+//     owns (row, pair) items and overwrites V[i][p], V[i][q].  Up to 112
+//     frames V sits in LDS beside G; in the 144-frame class (packed G alone
+//     takes 83.5 KB) it stays in the solve's V buffer in global memory,
+//     where it is rotated in place (the barriers of each round order the
+//     accesses, and the 166 KB stay in L2);
 //   * a round is [apply the round's rotations] barrier [the first wave
 //     computes the next round's rotations from the updated G] barrier.
 //
@@ -23,7 +27,8 @@
 // (W = G V goes through a per-solve global scratch buffer, since LDS holds G
 // and V already).  These classes serve FP32 solves only, so V is not
 // re-orthonormalised: the rounding of the rotations stays far below the
-// FP32 rounding of the data.
+// FP32 rounding of the data.  With V in global memory the projector
+// P = V diag(w) V^T is also formed on the f64 matrix cores.
 #include "common.h"
 #include "eig_common.h"
 #include "launch.h"
@@ -41,6 +46,7 @@ __device__ inline int pks(int i, int j) { return i <= j ? pk(i, j) : pk(j, i); }
 template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT)
 k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
+  constexpr bool VG = NMAX > kEigWideMaxN;  // V in global memory
   constexpr int NPK = NMAX * (NMAX + 1) / 2;
   constexpr int LDV = NMAX + 1;
   constexpr int NPM = NMAX / 2;                               // pairs per round at most
@@ -49,7 +55,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   constexpr int MV = (NMAX * NPM + NT - 1) / NT;              // V items per thread
   static_assert(NMAX % 2 == 0, "even class size");
   __shared__ double Gp[NPK];
-  __shared__ double Vs[NMAX * LDV];
+  __shared__ double Vs[VG ? 1 : NMAX * LDV];
   __shared__ int tp[NPM], tq[NPM];
   __shared__ double tc[NPM], ts[NPM], tdt[NPM];
   __shared__ double w[NMAX];
@@ -65,12 +71,24 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   const int kd = st->iter;
 
   const bool warm = kd > 0;
+  // V rows: LDS (stride LDV) or the solve's V buffer (stride nb, nb x nb,
+  // zero outside n x n)
+  const gptr<double> Vg = as_global<double>(static_cast<void*>(d.V));
   for (int idx = tid; idx < NPK; idx += NT) Gp[idx] = 0.0;
-  for (int idx = tid; idx < NMAX * LDV; idx += NT) {
-    const int i = idx / LDV, j = idx - (idx / LDV) * LDV;
-    double v = (i == j && i < n) ? 1.0 : 0.0;
-    if (warm && i < n && j < n) v = d.V[i * nb + j];
-    Vs[idx] = v;
+  if constexpr (VG) {
+    if (!warm) {
+      for (int idx = tid; idx < nb * nb; idx += NT) {
+        const int i = idx / nb, j = idx - (idx / nb) * nb;
+        Vg[idx] = (i == j && i < n) ? 1.0 : 0.0;
+      }
+    }
+  } else {
+    for (int idx = tid; idx < NMAX * LDV; idx += NT) {
+      const int i = idx / LDV, j = idx - (idx / LDV) * LDV;
+      double v = (i == j && i < n) ? 1.0 : 0.0;
+      if (warm && i < n && j < n) v = d.V[i * nb + j];
+      Vs[idx] = v;
+    }
   }
   if (tid < NMAX) w[tid] = 0.0;
   __syncthreads();
@@ -125,14 +143,16 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     constexpr int MT = (NUT + NWV - 1) / NWV;
     const int wv = tid >> 6, l = tid & 63;
     const gptr<double> Wg = as_global<double>(static_cast<void*>(d.escratch));
-    for (int t = wv; t < NT16 * NT16; t += NWV) {
-      const int bi = t / NT16, bj = t - (t / NT16) * NT16;
+    // with V in global memory the products stop at nb (V is nb x nb)
+    const int nt16 = VG ? nb / 16 : NT16;
+    for (int t = wv; t < nt16 * nt16; t += NWV) {
+      const int bi = t / nt16, bj = t - (t / nt16) * nt16;
       d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-      for (int kk = 0; kk < NMAX / 4; ++kk) {
+      for (int kk = 0; kk < nt16 * 4; ++kk) {
         const int kq = 4 * kk + (l >> 4);
         const double a = Gp[pks(16 * bi + (l & 15), kq)];
-        const double b = Vs[kq * LDV + 16 * bj + (l & 15)];
+        const double b = VG ? Vg[kq * nb + 16 * bj + (l & 15)] : Vs[kq * LDV + 16 * bj + (l & 15)];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
 #pragma unroll
@@ -151,11 +171,11 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
       tbj[q] = bj;
       tbi[q] = t < NUT ? t - bj * (bj + 1) / 2 : 0;
       gt[q] = d4{0.0, 0.0, 0.0, 0.0};
-      if (t < NUT) {
+      if (t < NUT && 16 * bj < nt16 * 16) {
 #pragma unroll 4
-        for (int kk = 0; kk < NMAX / 4; ++kk) {
+        for (int kk = 0; kk < nt16 * 4; ++kk) {
           const int kq = 4 * kk + (l >> 4);
-          const double a = Vs[kq * LDV + 16 * tbi[q] + (l & 15)];
+          const double a = VG ? Vg[kq * nb + 16 * tbi[q] + (l & 15)] : Vs[kq * LDV + 16 * tbi[q] + (l & 15)];
           const double b = Wg[kq * NMAX + 16 * bj + (l & 15)];
           gt[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gt[q], 0, 0, 0);
         }
@@ -163,7 +183,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     }
 #pragma unroll
     for (int q = 0; q < MT; ++q) {
-      if (wv + q * NWV < NUT) {
+      if (wv + q * NWV < NUT && 16 * tbj[q] < nt16 * 16) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * tbi[q] + (l >> 4) + 4 * r, j = 16 * tbj[q] + (l & 15);
@@ -260,11 +280,18 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
           const double s = ts[k];
           if (s != 0.0) {
             const double c = tc[k];
-            double* row = Vs + i * LDV;
             const int p = tp[k], qq = tq[k];
-            const double vp = row[p], vq = row[qq];
-            row[p] = fma(c, vp, -s * vq);
-            row[qq] = fma(s, vp, c * vq);
+            if constexpr (VG) {
+              const gptr<double> row = Vg + static_cast<size_t>(i) * nb;
+              const double vp = row[p], vq = row[qq];
+              row[p] = fma(c, vp, -s * vq);
+              row[qq] = fma(s, vp, c * vq);
+            } else {
+              double* row = Vs + i * LDV;
+              const double vp = row[p], vq = row[qq];
+              row[p] = fma(c, vp, -s * vq);
+              row[qq] = fma(s, vp, c * vq);
+            }
           }
         }
       }
@@ -281,23 +308,55 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   }
   __syncthreads();
   const gptr<T> Pd = as_global<T>(d.P);
-  const int nbup = nb * (nb + 1) / 2;
-  for (int idx = tid; idx < nbup; idx += NT) {
-    int j = 0;
-    while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-    const int i = idx - j * (j + 1) / 2;
-    double s = 0.0;
-    if (j < n) {
-      const double* vi_ = Vs + i * LDV;
-      const double* vj_ = Vs + j * LDV;
-      s = dot4<NMAX>([&](int k, double acc) { return fma(vi_[k] * w[k], vj_[k], acc); });
+  if constexpr (VG) {
+    // upper 16 x 16 blocks of (V diag(w)) V^T on the f64 matrix cores; the
+    // f64 result of lane l, register r is entry (l/16 + 4r, l%16); entries
+    // with i <= j are written to both halves, so P is exactly symmetric
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int NWV = NT / 64;
+    const int wv = tid >> 6, l = tid & 63;
+    const int nt16 = nb / 16;
+    const int nut = nt16 * (nt16 + 1) / 2;
+    for (int t = wv; t < nut; t += NWV) {
+      int bj = 0;
+      while ((bj + 1) * (bj + 2) / 2 <= t) ++bj;
+      const int bi = t - bj * (bj + 1) / 2;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int kk = 0; kk < nt16 * 4; ++kk) {
+        const int kq = 4 * kk + (l >> 4);
+        const double a = Vg[(16 * bi + (l & 15)) * nb + kq] * w[kq];
+        const double b = Vg[(16 * bj + (l & 15)) * nb + kq];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * bi + (l >> 4) + 4 * r, j = 16 * bj + (l & 15);
+        if (i <= j) {
+          Pd[i * nb + j] = static_cast<T>(acc[r]);
+          Pd[j * nb + i] = static_cast<T>(acc[r]);
+        }
+      }
     }
-    Pd[i * nb + j] = static_cast<T>(s);
-    Pd[j * nb + i] = static_cast<T>(s);
-  }
-  for (int idx = tid; idx < nb * nb; idx += NT) {
-    const int i = idx / nb, j = idx - (idx / nb) * nb;
-    d.V[idx] = (i < n && j < n) ? Vs[i * LDV + j] : 0.0;
+  } else {
+    const int nbup = nb * (nb + 1) / 2;
+    for (int idx = tid; idx < nbup; idx += NT) {
+      int j = 0;
+      while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+      const int i = idx - j * (j + 1) / 2;
+      double s = 0.0;
+      if (j < n) {
+        const double* vi_ = Vs + i * LDV;
+        const double* vj_ = Vs + j * LDV;
+        s = dot4<NMAX>([&](int k, double acc) { return fma(vi_[k] * w[k], vj_[k], acc); });
+      }
+      Pd[i * nb + j] = static_cast<T>(s);
+      Pd[j * nb + i] = static_cast<T>(s);
+    }
+    for (int idx = tid; idx < nb * nb; idx += NT) {
+      const int i = idx / nb, j = idx - (idx / nb) * nb;
+      d.V[idx] = (i < n && j < n) ? Vs[i * LDV + j] : 0.0;
+    }
   }
   if (tid == 0) {
     int rank = 0;
@@ -311,14 +370,18 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
 
 }  // namespace
 
-hipError_t launch_eig_wide(int dtype, int grid, hipStream_t stream, const SolveDesc* descs,
+hipError_t launch_eig_wide(int dtype, int ncls, int grid, hipStream_t stream, const SolveDesc* descs,
                            const int32_t* ids) {
   if (grid <= 0) return hipSuccess;
+  // these classes run FP32 solves only (FP64 register classes stop at 32)
+  if (dtype != 1) return hipErrorInvalidValue;
   const dim3 g(grid), b(kEigWideThreads);
-  if (dtype == 0)
-    RPCA_LAUNCH((k_eig_wide<double, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
-  else
+  if (ncls == kEigWideMaxN)
     RPCA_LAUNCH((k_eig_wide<float, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+  else if (ncls == kEigHugeMaxN)
+    RPCA_LAUNCH((k_eig_wide<float, kEigHugeMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -230,7 +230,7 @@ bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g) {
     g.tiles = static_cast<int>(tiles);
     g.tps = 1;  // one tile per work item (and per partial slot)
   } else {
-    if (dtype != RPCA_F32 || n > kEigWideMaxN) return false;
+    if (dtype != RPCA_F32 || n > kEigHugeMaxN) return false;
     g.nb = static_cast<int>((n + 15) / 16 * 16);
     const int64_t tiles = (m + kWideRows - 1) / kWideRows;
     g.tiles = static_cast<int>(tiles);
@@ -258,7 +258,10 @@ Big big_layout(int64_t m, int64_t n, const Geo& g) {
   b.P = o; o += al256(static_cast<size_t>(g.nb) * g.nb * g.es);
   b.V = o; o += al256(static_cast<size_t>(g.nb) * g.nb * sizeof(double));
   b.escratch = o;
-  if (n > kEigMaxN) o += al256(static_cast<size_t>(kEigWideMaxN) * kEigWideMaxN * sizeof(double));
+  if (n > kEigMaxN) {
+    const size_t c = static_cast<size_t>(eig_class(static_cast<int>(n)));
+    o += al256(c * c * sizeof(double));
+  }
   b.state = o; o += al256(sizeof(SolveState));
   b.trace = o;
 #ifdef RPCA_TRACE
@@ -292,7 +295,7 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
           for (int q = 0; q < recs[i]->geo.slots; ++q) items.push_back(WorkItem{i, q});
       lr.classes.push_back({key, {off, static_cast<int>(items.size()) - off}});
     }
-    for (int cls : {16, 32, 64, kEigWideMaxN}) {
+    for (int cls : {16, 32, 64, kEigWideMaxN, kEigHugeMaxN}) {
       const int off = static_cast<int>(ids.size());
       for (int i : lr.solves)
         if (eig_class(recs[i]->n) == cls) ids.push_back(i);
@@ -312,7 +315,7 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
       const int cnt = static_cast<int>(items.size()) - off;
       if (cnt > 0) lr.warm_classes.push_back({key, {off, cnt}});
     }
-    for (int cls : {16, 32, 64, kEigWideMaxN}) {
+    for (int cls : {16, 32, 64, kEigWideMaxN, kEigHugeMaxN}) {
       const int off = static_cast<int>(ids.size());
       for (int i : lr.solves)
         if (recs[i]->warm && eig_class(recs[i]->n) == cls) ids.push_back(i);
@@ -497,9 +500,9 @@ hipError_t enqueue_init(const Plan& plan, const Lanes& L) {
     EQ(launch_reduce(lr.gitem_cnt, s, plan.descs, plan.gitems + lr.gitem_off));
     // solves with a given start: fix mu, then the Gram of A_1 = X - S0 + Y0/mu
     for (const auto& er : lr.warm_eigs) {
-      if (er.first == kEigWideMaxN)
-        EQ(launch_eig_wide(plan.dtype == RPCA_F32 ? 1 : 0, er.second.second, s, plan.descs,
-                           plan.ids + er.second.first));
+      if (er.first > kEigMaxN)
+        EQ(launch_eig_wide(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s,
+                           plan.descs, plan.ids + er.second.first));
       else
         EQ(launch_eig(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s, plan.descs,
                       plan.ids + er.second.first));
@@ -521,9 +524,9 @@ static hipError_t enqueue_iterations_at(const Plan& plan, const Lanes& L, int it
     for (int k = 0; k < iters; ++k) {
       for (const auto& er : lr.eigs) {
         ev_begin(s, 1, first_iter + k, static_cast<int>(l), -1);
-        if (er.first == kEigWideMaxN)
-          EQ(launch_eig_wide(plan.dtype == RPCA_F32 ? 1 : 0, er.second.second, s, plan.descs,
-                             plan.ids + er.second.first));
+        if (er.first > kEigMaxN)
+          EQ(launch_eig_wide(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s,
+                             plan.descs, plan.ids + er.second.first));
         else
           EQ(launch_eig(plan.dtype == RPCA_F32 ? 1 : 0, er.first, er.second.second, s, plan.descs,
                         plan.ids + er.second.first));

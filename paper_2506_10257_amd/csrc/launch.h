@@ -49,13 +49,15 @@ hipError_t launch_reset_states(int count, hipStream_t stream, const SolveDesc* d
 // Eigensolver classes 16, 32 and 64: the largest n each handles.  The
 // workgroup size of each class (256, 512 or 1024 threads) is a tuning knob.
 // ids lists the solves (indices into descs) of the launch.
-// Returns 16, 32, 64 or kEigWideMaxN (0 if n is too large).
+// Returns 16, 32, 64, kEigWideMaxN or kEigHugeMaxN (0 if n is too large).
 int eig_class(int n);
-// Classes above 64 frames (up to kEigWideMaxN): the in-place eigensolver.
-hipError_t launch_eig_wide(int dtype, int grid, hipStream_t stream, const SolveDesc* descs,
-                           const int32_t* ids);
-// MFMA streaming kernel (FP32 storage): nb a multiple of 16 up to 112;
-// prec 0 = FP32 rebuild / FP64 Gram, 1 = split-BF16 (3 products) for both.
+// Classes above 64 frames: the in-place eigensolver, ncls = kEigWideMaxN
+// (V in LDS) or kEigHugeMaxN (V in global memory); FP32 solves only.
+hipError_t launch_eig_wide(int dtype, int ncls, int grid, hipStream_t stream,
+                           const SolveDesc* descs, const int32_t* ids);
+// MFMA streaming kernel (FP32 storage): nb a multiple of 16 up to 144;
+// prec 0 = FP32 rebuild / FP64 Gram, 1 = split-BF16 (3 products) for both,
+// 2 = split-BF16 (6 products).
 hipError_t launch_wide(int nb, int mode, int prec, int grid, hipStream_t stream,
                        const SolveDesc* descs, const WorkItem* items);
 bool eig_threads_valid(int ncls, int nt);

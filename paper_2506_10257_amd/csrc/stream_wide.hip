@@ -1,6 +1,6 @@
 // MFMA streaming kernel of the RPCA iteration (paper Sec. II-A, Eqs. 4-6) for
-// FP32 storage: every frame class up to 112 frames, and every class in the
-// split-BF16 precision variant.
+// FP32 storage: every frame class up to 144 frames, and every class in the
+// split-BF16 precision variants.
 //
 // A workgroup (8 wavefronts) walks a contiguous run of 64-row tiles of one
 // solve.  Per tile:
@@ -11,7 +11,9 @@
 //   2. rebuild L^T = P A^T on the matrix cores into a second LDS tile (P is
 //      symmetric); each 16-frame output block is shared by NW / NT16 waves
 //      (by 16-row blocks), which keep their rows of P in registers for the
-//      whole launch;
+//      whole launch.  With more blocks than waves (144 frames) wave w owns
+//      block w and the extra blocks are split by 16-row block over the first
+//      waves;
 //   3. read back each thread's L entries and apply the fused elementwise
 //      step (shrink, dual update, residual, next A) exactly as the register
 //      kernel does; the next A overwrites the A tile;
@@ -104,7 +106,7 @@ __device__ inline void split_any(float x, __bf16& hi, __bf16& mid, __bf16& lo) {
 template <int NB, int PHASE, int PREC>
 __global__ void __launch_bounds__(waves_for(NB) * 64)
 k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
-  static_assert(NB % 16 == 0 && NB <= 128, "frame class");
+  static_assert(NB % 16 == 0 && NB <= 144, "frame class");
   constexpr int NW = waves_for(NB);
   constexpr int NTH = NW * 64;
   constexpr int NQ = NB / NW;                           // frames per thread
@@ -162,9 +164,15 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
 
   // Rebuild work: frame block t = w mod NT16 and every NREP-th 16-row block
   // of the tile starting at w / NT16, so all waves share the rebuild when the
-  // class has fewer frame blocks than waves.
-  constexpr int NOWN = 1;
-  constexpr int NREP = NW / NT16;
+  // class has fewer frame blocks than waves.  With more blocks than waves
+  // (XTRA), wave w owns block w for every row block, and the 16-row blocks of
+  // the extra blocks NW, NW+1, ... go one each to waves 0, 1, ...
+  constexpr bool XTRA = NT16 > NW;
+  static_assert(!XTRA || 4 * (NT16 - NW) <= NW, "extra frame blocks exceed the waves");
+  constexpr int NOWN = XTRA ? 2 : 1;
+  constexpr int NREP = XTRA ? 1 : NW / NT16;
+  const int own_t[2] = {XTRA ? w : w % NT16, NW + (w >> 2)};
+  const bool owns[2] = {XTRA || w < NT16 * NREP, XTRA && w < 4 * (NT16 - NW)};
   float pa[PREC ? 1 : NOWN][PREC ? 1 : NK4];
   bf8 ph[PREC ? NOWN : 1][PREC ? NKB : 1], pl[PREC ? NOWN : 1][PREC ? NKB : 1];
   bf8 pm[X6 ? NOWN : 1][X6 ? NKB : 1];
@@ -172,8 +180,8 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
     const gptr<const float> P = as_global<float>(static_cast<const void*>(d.P));
 #pragma unroll
     for (int o = 0; o < NOWN; ++o) {
-      const int t = w % NT16 + NW * o;
-      const int prow = 16 * (t < NT16 ? t : 0) + (l & 15);
+      const int t = own_t[o];
+      const int prow = 16 * (owns[o] ? t : 0) + (l & 15);
       if constexpr (PREC == 0) {
 #pragma unroll
         for (int kk = 0; kk < NK4; ++kk) pa[o][kk] = P[prow * NB + 4 * kk + (l >> 4)];
@@ -309,10 +317,12 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
       // 2. rebuild L^T = P A^T into Lt
 #pragma unroll
       for (int o = 0; o < NOWN; ++o) {
-        const int t = w % NT16 + NW * o;
-        if (w < NT16 * NREP) {
+        const int t = own_t[o];
+        if (owns[o]) {
+          const int rb0 = o == 0 ? (XTRA ? 0 : w / NT16) : (w & 3);
+          const int rstep = o == 0 ? NREP : R / 16;
 #pragma unroll 1
-          for (int rb = w / NT16; rb < R / 16; rb += NREP) {
+          for (int rb = rb0; rb < R / 16; rb += rstep) {
             f4 acc = {0.f, 0.f, 0.f, 0.f};
             if constexpr (PREC == 0) {
 #pragma unroll
@@ -470,11 +480,11 @@ hipError_t launch_wide(int nb, int mode, int prec, int grid, hipStream_t stream,
     return hipGetLastError();                                                                  \
   }
   RPCA_WIDE(16, 0) RPCA_WIDE(32, 0) RPCA_WIDE(48, 0) RPCA_WIDE(64, 0)
-  RPCA_WIDE(80, 0) RPCA_WIDE(96, 0) RPCA_WIDE(112, 0)
+  RPCA_WIDE(80, 0) RPCA_WIDE(96, 0) RPCA_WIDE(112, 0) RPCA_WIDE(128, 0) RPCA_WIDE(144, 0)
   RPCA_WIDE(16, 1) RPCA_WIDE(32, 1) RPCA_WIDE(48, 1) RPCA_WIDE(64, 1)
-  RPCA_WIDE(80, 1) RPCA_WIDE(96, 1) RPCA_WIDE(112, 1)
+  RPCA_WIDE(80, 1) RPCA_WIDE(96, 1) RPCA_WIDE(112, 1) RPCA_WIDE(128, 1) RPCA_WIDE(144, 1)
   RPCA_WIDE(16, 2) RPCA_WIDE(32, 2) RPCA_WIDE(48, 2) RPCA_WIDE(64, 2)
-  RPCA_WIDE(80, 2) RPCA_WIDE(96, 2) RPCA_WIDE(112, 2)
+  RPCA_WIDE(80, 2) RPCA_WIDE(96, 2) RPCA_WIDE(112, 2) RPCA_WIDE(128, 2) RPCA_WIDE(144, 2)
 #undef RPCA_WIDE
   return hipErrorInvalidValue;
 }

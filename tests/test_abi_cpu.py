@@ -54,7 +54,7 @@ def test_footprint(lib):
     assert 8 * mat32 <= f64 < 8 * mat32 + (8 << 20)
     assert lib.rpca_footprint_bytes(0, 20, _lib.RPCA_F32) == 0
     assert lib.rpca_footprint_bytes(100, 0, _lib.RPCA_F32) == 0
-    assert lib.rpca_footprint_bytes(100, 129, _lib.RPCA_F32) == 0
+    assert lib.rpca_footprint_bytes(100, 145, _lib.RPCA_F32) == 0
     assert lib.rpca_footprint_bytes(100, 20, 7) == 0
 
 
@@ -71,7 +71,7 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert _call(lib, A, 100, 4, B, None)[0] == _lib.RPCA_ERR_ARG
     assert _call(lib, A, 0, 4, B, C)[0] == _lib.RPCA_ERR_ARG
     assert _call(lib, A, 100, 0, B, C)[0] == _lib.RPCA_ERR_ARG
-    assert _call(lib, A, 100, 129, B, C)[0] == _lib.RPCA_ERR_ARG
+    assert _call(lib, A, 100, 145, B, C)[0] == _lib.RPCA_ERR_ARG
     assert _call(lib, A, 100, 4, B, C, maxit=0)[0] == _lib.RPCA_ERR_ARG
     # overlapping M / L / S
     assert _call(lib, A, 100, 4, A + 16, C)[0] == _lib.RPCA_ERR_ARG
@@ -112,12 +112,17 @@ def test_tuning_knobs(lib):
 
 def test_frame_limits(lib):
     A, B, C = 1 << 40, 2 << 40, 3 << 40
-    assert _lib.RPCA_N_MAX == 112
-    assert _call(lib, A, 100, 113, B, C)[0] == _lib.RPCA_ERR_ARG
+    assert _lib.RPCA_N_MAX == 144
+    assert _call(lib, A, 100, 145, B, C)[0] == _lib.RPCA_ERR_ARG
     assert _call(lib, A, 100, 33, B, C, fn="rpca_solve_f64")[0] == _lib.RPCA_ERR_UNSUPPORTED
-    assert lib.rpca_footprint_bytes(4096, 112, _lib.RPCA_F32) > 0
-    assert lib.rpca_footprint_bytes(4096, 113, _lib.RPCA_F32) == 0
+    for n in (112, 113, 128, 132, 144):
+        assert lib.rpca_footprint_bytes(4096, n, _lib.RPCA_F32) > 0
+    assert lib.rpca_footprint_bytes(4096, 145, _lib.RPCA_F32) == 0
     assert lib.rpca_footprint_bytes(4096, 33, _lib.RPCA_F64) == 0
+    # the 144-frame class holds a 144 x 144 FP64 scratch for the eigensolver's
+    # warm start beside its V, P and partials
+    assert (lib.rpca_footprint_bytes(4096, 132, _lib.RPCA_F32)
+            > lib.rpca_footprint_bytes(4096, 112, _lib.RPCA_F32) + 144 * 144 * 8)
     # the split-BF16 mode is FP32 only
     p = _lib.RpcaProblem()
     p.M, p.L, p.S, p.m, p.n, p.maxit = A, B, C, 100, 4, 10

@@ -1,6 +1,7 @@
-"""Windows of 65-112 frames (MFMA tile streaming kernel and the in-place
-eigensolver), the tile kernel on the smaller frame classes, and the
-split-BF16 precision variant, against the FP64 oracle.
+"""Windows of 65-144 frames (MFMA tile streaming kernel and the in-place
+eigensolver; above 112 frames its eigenvectors stay in device memory), the
+tile kernel on the smaller frame classes, and the split-BF16 precision
+variants, against the FP64 oracle.
 
 Bars as for the other FP32 paths: relative Frobenius error <= 1e-4 in L and
 S, iterations within one, Dice >= 0.999 on the bound-bubble mask.  The
@@ -36,8 +37,11 @@ def _check(name, w, ref, L, S, it, bar=1e-4, it_slack=1):
 
 
 # (H, W, n): ragged row counts (not a multiple of the 64-row tile), odd and
-# even frame counts, every wide class (80, 96, 112) and its edges.
-WIDE = [(48, 48, 65), (50, 47, 80), (40, 60, 81), (48, 49, 99), (44, 50, 100), (40, 52, 112)]
+# even frame counts, every wide class (80, 96, 112, 128, 144) and its edges;
+# 113-144 frames run the eigensolver with V in device memory, 132 is the
+# paper's reference window length.
+WIDE = [(48, 48, 65), (50, 47, 80), (40, 60, 81), (48, 49, 99), (44, 50, 100), (40, 52, 112),
+        (40, 41, 113), (36, 40, 120), (32, 40, 128), (40, 40, 129), (44, 40, 132), (40, 37, 144)]
 
 
 @pytest.mark.parametrize("H,W,n", WIDE)
@@ -50,17 +54,19 @@ def test_wide_fp32_matches_oracle(H, W, n):
     _check(f"wide {H}x{W}x{n}", w, ref, L, S, it)
 
 
+@pytest.mark.parametrize("n", [100, 132])
 @pytest.mark.parametrize("k", [1, 2, 7])
-def test_wide_iterate_parity(k):
-    """Fixed iteration counts (tol = 0): the k-th iterate against the oracle's."""
+def test_wide_iterate_parity(n, k):
+    """Fixed iteration counts (tol = 0): the k-th iterate against the oracle's
+    (k >= 2 runs the eigensolver's warm start)."""
     device()
-    w = batch_window(40, 40, 100, 7101)
+    w = batch_window(40, 40, n, 7101 + n)
     X = w.X()
     ref = rpca(X, tol=0.0, maxit=k)
     L, S, it, rc = _solve(X, tol=0.0, maxit=k)
     assert it == k and rc == rp.RPCA_NOT_CONVERGED
     eL, eS = rel_fro(L, ref.L), rel_fro(S, ref.S)
-    report(f"wide iterate k={k}", relL=eL, relS=eS)
+    report(f"wide iterate n={n} k={k}", relL=eL, relS=eS)
     assert eL <= 1e-5 and eS <= 1e-5
 
 
@@ -94,7 +100,8 @@ def test_zero_input_wide():
 def test_wide_batch_bitwise_equals_alone():
     import torch
     device()
-    shapes = [(40, 40, 100), (32, 48, 20), (48, 40, 80), (30, 30, 112), (64, 64, 10)]
+    shapes = [(40, 40, 100), (32, 48, 20), (48, 40, 80), (30, 30, 112), (64, 64, 10), (40, 44, 132),
+              (36, 36, 113)]
     Ms = [to_dev(batch_window(H, W, n, 7300 + i).X(), np.float32) for i, (H, W, n) in enumerate(shapes)]
     alone = [rp.solve(M, tol=1e-6, maxit=200) for M in Ms]
     many = rp.solve_many(Ms, tol=1e-6, maxit=200)
@@ -104,7 +111,7 @@ def test_wide_batch_bitwise_equals_alone():
         assert torch.equal(a.L, b.L) and torch.equal(a.S, b.S)
 
 
-@pytest.mark.parametrize("H,W,n", [(64, 64, 40), (48, 50, 100)])
+@pytest.mark.parametrize("H,W,n", [(64, 64, 40), (48, 50, 100), (44, 40, 132)])
 def test_bf16x3_error_stated(H, W, n):
     """Split-BF16 contractions: the error against the FP64 oracle is measured
     and reported; the bound only catches a broken kernel."""
@@ -140,7 +147,7 @@ def test_precision_window_fp32_and_bf16x3():
     assert eL <= 2e-2 and eS <= 2e-2 and d >= 0.99
 
 
-@pytest.mark.parametrize("H,W,n", [(128, 128, 40), (48, 50, 100), (64, 72, 20)])
+@pytest.mark.parametrize("H,W,n", [(128, 128, 40), (48, 50, 100), (64, 72, 20), (44, 40, 132)])
 def test_bf16x6_meets_fp32_bar(H, W, n):
     """Three-way split BF16 contractions (six products): held to the FP32 bar."""
     from synth import make_window, density_counts
