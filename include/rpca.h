@@ -52,7 +52,7 @@ extern "C" {
 #define RPCA_ERR_NOMEM         -2  /* device allocation failed               */
 #define RPCA_ERR_DEVICE        -3  /* HIP runtime error                      */
 #define RPCA_ERR_NONFINITE     -4  /* NaN or Inf in M (or in the iteration)  */
-#define RPCA_ERR_UNSUPPORTED   -5  /* shape not supported by this build      */
+#define RPCA_ERR_UNSUPPORTED   -5  /* shape not supported by the library     */
 /* Negative codes leave L and S unspecified. */
 
 /* ---- element types and contraction modes -------------------------------- */

@@ -52,7 +52,6 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   constexpr int NPM = NMAX / 2;                               // pairs per round at most
   constexpr int NBLK = NPM * (NPM + 1) / 2;                   // 2x2 blocks (k1 <= k2)
   constexpr int MB = (NBLK + NT - 1) / NT;                    // blocks per thread
-  constexpr int MV = (NMAX * NPM + NT - 1) / NT;              // V items per thread
   static_assert(NMAX % 2 == 0, "even class size");
   __shared__ double Gp[NPK];
   __shared__ double Vs[VG ? 1 : NMAX * LDV];
@@ -200,7 +199,8 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   const int nblk2 = NP * (NP + 1) / 2;
 
   // Owned 2x2 blocks (pair indices k1 <= k2) and V items (row, pair).
-  int bk1[MB], bk2[MB], vi[MV], vk[MV];
+  // 2x2 blocks packed as k1 | k2 << 8
+  int bk[MB];
 #pragma unroll
   for (int q = 0; q < MB; ++q) {
     const int b = tid + q * NT;
@@ -208,15 +208,15 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     if (b < nblk2) {
       while ((k2 + 1) * (k2 + 2) / 2 <= b) ++k2;
     }
-    bk2[q] = k2;
-    bk1[q] = b < nblk2 ? b - k2 * (k2 + 1) / 2 : 0;
+    bk[q] = (b < nblk2 ? b - k2 * (k2 + 1) / 2 : 0) | (k2 << 8);
   }
-#pragma unroll
-  for (int q = 0; q < MV; ++q) {
-    const int it = tid + q * NT;
-    vk[q] = NP > 0 ? it % NP : 0;
-    vi[q] = NP > 0 ? it / NP : n;
-  }
+  // V items: thread tid rotates pair vk = tid mod NP of rows vr0, vr0 + vrs,
+  // ... (vrs = NT / NP threads share a pair), so it reads its pair's rotation
+  // once per round
+  const int vrs = NP > 0 ? NT / NP : 1;
+  const int vk = NP > 0 ? tid % NP : 0;
+  const int vr0 = NP > 0 ? tid / NP : n;
+  const bool vact = NP > 0 && vr0 < vrs;
 
   // Rotations of round r for pairs handled by the first wave.
   auto make_round = [&](int r) {
@@ -245,52 +245,95 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     make_round(0);
     if (!__syncthreads_or(need)) break;
     for (int r = 0; r < M; ++r) {
-      // apply round r: G blocks and V items, in place
+      // apply round r: G blocks and V items, in place.  The items of a
+      // thread are disjoint from each other (and from every other thread's),
+      // so all reads of a group of items are issued before its writes;
+      // otherwise each read would wait behind the previous item's write.
+      double gv[MB][4];
+      int gi[MB][4], gmode[MB];
 #pragma unroll
       for (int q = 0; q < MB; ++q) {
+        gmode[q] = 0;
         if (tid + q * NT < nblk2) {
-          const int k1 = bk1[q], k2 = bk2[q];
+          const int k1 = bk[q] & 0xff, k2 = bk[q] >> 8;
           const int p1 = tp[k1], q1 = tq[k1], p2 = tp[k2], q2 = tq[k2];
-          const double c1 = tc[k1], s1 = ts[k1], c2 = tc[k2], s2 = ts[k2];
+          const double s1 = ts[k1], s2 = ts[k2];
           if (k1 == k2) {
             if (s1 != 0.0) {
-              const double dt = tdt[k1];
-              Gp[pk(p1, p1)] -= dt;
-              Gp[pk(q1, q1)] += dt;
-              Gp[pk(p1, q1)] = 0.0;
+              gmode[q] = 1;
+              gi[q][0] = pk(p1, p1);
+              gi[q][1] = pk(q1, q1);
+              gi[q][2] = pk(p1, q1);
+              gv[q][0] = Gp[gi[q][0]];
+              gv[q][1] = Gp[gi[q][1]];
             }
           } else if (s1 != 0.0 || s2 != 0.0) {
-            const int ia = pks(p1, p2), ib = pks(p1, q2), ic = pks(q1, p2), id = pks(q1, q2);
-            const double b_pp = Gp[ia], b_pq = Gp[ib], b_qp = Gp[ic], b_qq = Gp[id];
-            // T = B J2 (columns p2, q2), then J1^T T (rows p1, q1)
-            const double t_pp = fma(c2, b_pp, -s2 * b_pq), t_pq = fma(s2, b_pp, c2 * b_pq);
-            const double t_qp = fma(c2, b_qp, -s2 * b_qq), t_qq = fma(s2, b_qp, c2 * b_qq);
-            Gp[ia] = fma(c1, t_pp, -s1 * t_qp);
-            Gp[ib] = fma(c1, t_pq, -s1 * t_qq);
-            Gp[ic] = fma(s1, t_pp, c1 * t_qp);
-            Gp[id] = fma(s1, t_pq, c1 * t_qq);
+            gmode[q] = 2;
+            gi[q][0] = pks(p1, p2);
+            gi[q][1] = pks(p1, q2);
+            gi[q][2] = pks(q1, p2);
+            gi[q][3] = pks(q1, q2);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) gv[q][e] = Gp[gi[q][e]];
           }
         }
       }
 #pragma unroll
-      for (int q = 0; q < MV; ++q) {
-        const int i = vi[q];
-        if (i < n) {
-          const int k = vk[q];
-          const double s = ts[k];
-          if (s != 0.0) {
-            const double c = tc[k];
-            const int p = tp[k], qq = tq[k];
-            if constexpr (VG) {
-              const gptr<double> row = Vg + static_cast<size_t>(i) * nb;
-              const double vp = row[p], vq = row[qq];
-              row[p] = fma(c, vp, -s * vq);
-              row[qq] = fma(s, vp, c * vq);
-            } else {
-              double* row = Vs + i * LDV;
-              const double vp = row[p], vq = row[qq];
-              row[p] = fma(c, vp, -s * vq);
-              row[qq] = fma(s, vp, c * vq);
+      for (int q = 0; q < MB; ++q) {
+        if (gmode[q] == 1) {
+          const double dt = tdt[bk[q] & 0xff];
+          Gp[gi[q][0]] = gv[q][0] - dt;
+          Gp[gi[q][1]] = gv[q][1] + dt;
+          Gp[gi[q][2]] = 0.0;
+        } else if (gmode[q] == 2) {
+          const int k1 = bk[q] & 0xff, k2 = bk[q] >> 8;
+          const double c1 = tc[k1], s1 = ts[k1], c2 = tc[k2], s2 = ts[k2];
+          const double b_pp = gv[q][0], b_pq = gv[q][1], b_qp = gv[q][2], b_qq = gv[q][3];
+          // T = B J2 (columns p2, q2), then J1^T T (rows p1, q1)
+          const double t_pp = fma(c2, b_pp, -s2 * b_pq), t_pq = fma(s2, b_pp, c2 * b_pq);
+          const double t_qp = fma(c2, b_qp, -s2 * b_qq), t_qq = fma(s2, b_qp, c2 * b_qq);
+          Gp[gi[q][0]] = fma(c1, t_pp, -s1 * t_qp);
+          Gp[gi[q][1]] = fma(c1, t_pq, -s1 * t_qq);
+          Gp[gi[q][2]] = fma(s1, t_pp, c1 * t_qp);
+          Gp[gi[q][3]] = fma(s1, t_pq, c1 * t_qq);
+        }
+      }
+      constexpr int VC = 4;  // V rows read together
+      if (vact && ts[vk] != 0.0) {
+        const double sk = ts[vk], ck = tc[vk];
+        const int p = tp[vk], qq = tq[vk];
+        for (int i0 = vr0; i0 < n; i0 += VC * vrs) {
+          double vp[VC], vq[VC];
+#pragma unroll
+          for (int u = 0; u < VC; ++u) {
+            const int i = i0 + u * vrs;
+            vp[u] = 0.0;
+            vq[u] = 0.0;
+            if (i < n) {
+              if constexpr (VG) {
+                const gptr<double> row = Vg + static_cast<size_t>(i) * nb;
+                vp[u] = row[p];
+                vq[u] = row[qq];
+              } else {
+                vp[u] = Vs[i * LDV + p];
+                vq[u] = Vs[i * LDV + qq];
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < VC; ++u) {
+            const int i = i0 + u * vrs;
+            if (i < n) {
+              const double np_ = fma(ck, vp[u], -sk * vq[u]);
+              const double nq_ = fma(sk, vp[u], ck * vq[u]);
+              if constexpr (VG) {
+                const gptr<double> row = Vg + static_cast<size_t>(i) * nb;
+                row[p] = np_;
+                row[qq] = nq_;
+              } else {
+                Vs[i * LDV + p] = np_;
+                Vs[i * LDV + qq] = nq_;
+              }
             }
           }
         }

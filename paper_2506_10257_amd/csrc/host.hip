@@ -943,7 +943,7 @@ const char* rpca_strerror(int code) {
     case RPCA_ERR_NOMEM: return "device memory allocation failed";
     case RPCA_ERR_DEVICE: return "HIP runtime error";
     case RPCA_ERR_NONFINITE: return "non-finite value in the input or the iteration";
-    case RPCA_ERR_UNSUPPORTED: return "shape not supported by this build";
+    case RPCA_ERR_UNSUPPORTED: return "shape not supported by the library";
     default: return "unknown status";
   }
 }
