@@ -205,6 +205,22 @@ int rpca_profile_read(rpca_profile* out, int reset);
  *                           the FP32 bar); a solve's result never depends on
  *                           what else runs with it.                          */
 #define RPCA_KNOB_STREAM_KERNEL 2
+/*   RPCA_KNOB_TILE_ROWS     pixel rows each workgroup of the tile kernel
+ *                           walks (its tile shape along m) for one tile class
+ *                           (`cls` = nb = 16, 32, ..., 144, the frame count
+ *                           rounded up to 16; dtype RPCA_F32): a multiple of
+ *                           64 from 64 to 8192.  Fewer rows give more workgroups
+ *                           (better occupancy for small launches), more rows
+ *                           amortise the workgroup's Gram partial.  The
+ *                           default is 1024.  A solve of m rows uses at most
+ *                           max(256, m / 256) rows per workgroup (rounded
+ *                           down to 64), so it spreads over at least one
+ *                           workgroup per CU.  The partial sums are
+ *                           grouped by workgroup, so results differ between
+ *                           settings by rounding (within the FP32 bar); for
+ *                           a given setting they are the same alone or in a
+ *                           batch.                                          */
+#define RPCA_KNOB_TILE_ROWS 3
 int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value);
 int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls);
 
@@ -284,7 +300,10 @@ void rpca_server_destroy(rpca_server* s);
  *   - RPCA_KNOB_EIG_THREADS per eigensolver class, on a 16384 x cls window;
  *   - RPCA_KNOB_STREAM_KERNEL per FP32 register class of 16 frames or more,
  *     on a `rows` x cls window (rows >= 256; e.g. 262144 for 512 x 512
- *     images).
+ *     images);
+ *   - then RPCA_KNOB_TILE_ROWS for every tile class the tile kernel serves
+ *     (the classes above 64 frames and those of the register classes now on
+ *     the tile kernel), on a `rows` x n window of that class.
  * It allocates its windows with hipMalloc and frees them before returning.
  * It uses the kernel-timing accumulators (rpca_profile_*), which it resets,
  * so it must not run while other calls use them.  Returns RPCA_OK, or the

@@ -26,6 +26,7 @@ RPCA_GRAM_BF16X6 = 2
 RPCA_N_MAX = 144
 RPCA_KNOB_EIG_THREADS = 1
 RPCA_KNOB_STREAM_KERNEL = 2
+RPCA_KNOB_TILE_ROWS = 3
 RPCA_SERVER_SIMULATE = 1
 
 EXPORTS = (

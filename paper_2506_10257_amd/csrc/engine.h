@@ -131,5 +131,8 @@ int nb_class(int64_t n, int dtype);
 // FP32 register classes: streaming kernel choice (0 register, 1 MFMA tiles).
 int stream_kernel_choice(int cls);
 bool set_stream_kernel_choice(int cls, int v);
+// rows per workgroup of the tile kernel for tile class nb (-1: no such class)
+int tile_rows(int nb);
+bool set_tile_rows(int nb, int rows);
 
 }  // namespace rpca

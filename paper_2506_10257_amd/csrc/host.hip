@@ -202,6 +202,28 @@ int nb_class(int64_t n, int dtype) {
   return 0;
 }
 
+// Rows per workgroup of the tile kernel, per tile class nb = 16 (i + 1).
+std::atomic<int> g_tile_rows[kEigHugeMaxN / 16];
+std::once_flag g_tile_rows_once;
+void init_tile_rows() {
+  std::call_once(g_tile_rows_once, [] {
+    for (int i = 0; i < kEigHugeMaxN / 16; ++i) g_tile_rows[i].store(1024);
+  });
+}
+
+int tile_rows(int nb) {
+  if (nb < 16 || nb > kEigHugeMaxN || nb % 16 != 0) return -1;
+  init_tile_rows();
+  return g_tile_rows[nb / 16 - 1].load(std::memory_order_relaxed);
+}
+
+bool set_tile_rows(int nb, int rows) {
+  if (tile_rows(nb) < 0) return false;
+  if (rows < kWideRows || rows > 8192 || rows % kWideRows != 0) return false;
+  g_tile_rows[nb / 16 - 1].store(rows, std::memory_order_relaxed);
+  return true;
+}
+
 int stream_kernel_choice(int cls) {
   if (cls < 0 || cls > kEigMaxN) return -1;
   for (int c : kClassesF32)
@@ -234,9 +256,12 @@ bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g) {
     g.nb = static_cast<int>((n + 15) / 16 * 16);
     const int64_t tiles = (m + kWideRows - 1) / kWideRows;
     g.tiles = static_cast<int>(tiles);
-    // rows per workgroup: at least 16 per frame, so the O(nb^2) Gram partial
-    // stays a few percent of the workgroup's streamed bytes
-    const int rows = std::max(1024, 16 * g.nb);
+    // rows per workgroup: the tuning knob of the class (1024 by default, so
+    // the O(nb^2) Gram partial stays a few percent of the workgroup's
+    // streamed bytes), capped so that the solve spreads over at least 256
+    // workgroups (one per CU) where it has 256 rows each to give
+    const int64_t cap = std::max<int64_t>(4 * kWideRows, (m / 256) / kWideRows * kWideRows);
+    const int rows = static_cast<int>(std::min<int64_t>(tile_rows(g.nb), cap));
     g.tps = (rows + kWideRows - 1) / kWideRows;
   }
   g.slots = (g.tiles + g.tps - 1) / g.tps;
@@ -957,6 +982,10 @@ int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value) {
     if (dtype != RPCA_F32) return RPCA_ERR_ARG;
     return set_stream_kernel_choice(cls, value) ? RPCA_OK : RPCA_ERR_ARG;
   }
+  if (knob == RPCA_KNOB_TILE_ROWS) {
+    if (dtype != RPCA_F32) return RPCA_ERR_ARG;
+    return set_tile_rows(cls, value) ? RPCA_OK : RPCA_ERR_ARG;
+  }
   return RPCA_ERR_ARG;
 }
 
@@ -970,6 +999,11 @@ int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls) {
     if (dtype != RPCA_F32) return RPCA_ERR_ARG;
     const int v = stream_kernel_choice(cls);
     return v >= 0 ? v : RPCA_ERR_ARG;
+  }
+  if (knob == RPCA_KNOB_TILE_ROWS) {
+    if (dtype != RPCA_F32) return RPCA_ERR_ARG;
+    const int v = tile_rows(cls);
+    return v > 0 ? v : RPCA_ERR_ARG;
   }
   return RPCA_ERR_ARG;
 }

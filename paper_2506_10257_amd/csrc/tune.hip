@@ -8,7 +8,9 @@
 //     arithmetic, so only time differs);
 //   * streaming kernel (thread-per-row register kernel or the MFMA tile
 //     kernel) per FP32 register frame class, timed on a window of `rows`
-//     pixel rows.
+//     pixel rows;
+//   * the tile shape of the tile kernel (pixel rows per workgroup) for every
+//     tile class that runs it after the step above, timed the same way.
 // The synthetic window is a hash-noise matrix with a rank-one background,
 // written by a device kernel; timing does not depend on its values except
 // through the number of Jacobi sweeps, which is the same for every variant
@@ -172,6 +174,45 @@ int rpca_autotune(int32_t dtype, int64_t rows, void* stream) {
       if (rc < 0) return rc;
     }
   }
+
+  // 3. rows per workgroup of the tile kernel, per tile class that runs it:
+  // every class above 64 frames, and the classes of the register frame
+  // counts whose kernel choice is now the tile kernel (timed with that frame
+  // count, so the solve takes the tile kernel)
+  if (dtype == RPCA_F32) {
+    for (int nb = 16; nb <= kEigHugeMaxN; nb += 16) {
+      int n = 0;
+      if (nb > kEigMaxN) {
+        n = nb;
+      } else {
+        for (int c : kClassesF32)
+          if ((c + 15) / 16 * 16 == nb && rpca_tune_get(RPCA_KNOB_STREAM_KERNEL, dtype, c) == 1) n = c;
+      }
+      if (n == 0) continue;
+      Bufs b;
+      rc = alloc_window(b, rows, n, dtype, s);
+      if (rc != RPCA_OK) {
+        free_window(b);
+        return rc;
+      }
+      const int old = rpca_tune_get(RPCA_KNOB_TILE_ROWS, dtype, nb);
+      int best = old;
+      double best_ms = 1e30;
+      for (int tr : {256, 512, 1024, 2048, 4096}) {
+        if (rpca_tune_set(RPCA_KNOB_TILE_ROWS, dtype, nb, tr) != RPCA_OK) continue;
+        double eig_ms = 0, upd_ms = 0;
+        rc = time_solve(b, rows, n, dtype, kTuneIters, s, eig_ms, upd_ms);
+        if (rc < 0) break;
+        if (upd_ms < best_ms) {
+          best_ms = upd_ms;
+          best = tr;
+        }
+      }
+      (void)rpca_tune_set(RPCA_KNOB_TILE_ROWS, dtype, nb, rc < 0 ? old : best);
+      free_window(b);
+      if (rc < 0) return rc;
+    }
+  }
   return RPCA_OK;
 }
 
@@ -187,6 +228,9 @@ int rpca_autotune_save(const char* path) {
   for (int cls : kClassesF32)
     std::fprintf(f, "%d %d %d %d\n", RPCA_KNOB_STREAM_KERNEL, RPCA_F32, cls,
                  rpca_tune_get(RPCA_KNOB_STREAM_KERNEL, RPCA_F32, cls));
+  for (int nb = 16; nb <= kEigHugeMaxN; nb += 16)
+    std::fprintf(f, "%d %d %d %d\n", RPCA_KNOB_TILE_ROWS, RPCA_F32, nb,
+                 rpca_tune_get(RPCA_KNOB_TILE_ROWS, RPCA_F32, nb));
   const int ok = std::fclose(f) == 0;
   return ok ? RPCA_OK : RPCA_ERR_ARG;
 }

@@ -147,6 +147,50 @@ def test_stream_kernel_knob(lib):
     assert rp.rpca_tune_get(K, rp.RPCA_F64, 20) == rp.RPCA_ERR_ARG
 
 
+def test_tile_rows_knob(lib):
+    import paper_2506_10257_amd as rp
+    K = rp.RPCA_KNOB_TILE_ROWS
+    for nb in range(16, 145, 16):
+        assert rp.rpca_tune_get(K, rp.RPCA_F32, nb) == 1024
+    old = rp.rpca_tune_get(K, rp.RPCA_F32, 64)
+    try:
+        for rows in (64, 256, 512, 768, 1024, 2048, 4096, 8192):
+            assert rp.rpca_tune_set(K, rp.RPCA_F32, 64, rows) == rp.RPCA_OK
+            assert rp.rpca_tune_get(K, rp.RPCA_F32, 64) == rows
+    finally:
+        assert rp.rpca_tune_set(K, rp.RPCA_F32, 64, old) == rp.RPCA_OK
+    for bad in (0, 32, 100, 8256):
+        assert rp.rpca_tune_set(K, rp.RPCA_F32, 64, bad) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 40, 512) == rp.RPCA_ERR_ARG   # not a tile class
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, 160, 512) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_set(K, rp.RPCA_F64, 64, 512) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_get(K, rp.RPCA_F64, 64) == rp.RPCA_ERR_ARG
+    assert rp.rpca_tune_get(K, rp.RPCA_F32, 64) == old
+
+
+def test_tile_rows_change_the_footprint(lib):
+    """Fewer rows per workgroup mean more partial slots in the workspace."""
+    import paper_2506_10257_amd as rp
+    K = rp.RPCA_KNOB_TILE_ROWS
+    old = rp.rpca_tune_get(K, rp.RPCA_F32, 112)
+    try:
+        big = lib.rpca_footprint_bytes(262144, 100, rp.RPCA_F32)
+        assert rp.rpca_tune_set(K, rp.RPCA_F32, 112, 256) == rp.RPCA_OK
+        small = lib.rpca_footprint_bytes(262144, 100, rp.RPCA_F32)
+    finally:
+        rp.rpca_tune_set(K, rp.RPCA_F32, 112, old)
+    assert small > big
+    assert lib.rpca_footprint_bytes(262144, 100, rp.RPCA_F32) == big
+    # a 65536-row window is capped at 256 rows per workgroup (256 workgroups),
+    # whatever the knob says
+    try:
+        capped = lib.rpca_footprint_bytes(65536, 100, rp.RPCA_F32)
+        assert rp.rpca_tune_set(K, rp.RPCA_F32, 112, 256) == rp.RPCA_OK
+        assert lib.rpca_footprint_bytes(65536, 100, rp.RPCA_F32) == capped
+    finally:
+        rp.rpca_tune_set(K, rp.RPCA_F32, 112, old)
+
+
 def test_autotune_save_load_roundtrip(lib, tmp_path):
     import paper_2506_10257_amd as rp
     K, S = rp.RPCA_KNOB_EIG_THREADS, rp.RPCA_KNOB_STREAM_KERNEL
@@ -156,6 +200,7 @@ def test_autotune_save_load_roundtrip(lib, tmp_path):
     try:
         rp.rpca_tune_set(K, rp.RPCA_F32, 64, 256)
         rp.rpca_tune_set(S, rp.RPCA_F32, 40, 1 - before["stream_kernel"][40])
+        rp.rpca_tune_set(rp.RPCA_KNOB_TILE_ROWS, rp.RPCA_F32, 96, 512)
         assert rp.tuning_choices() != before
         assert rp.rpca_autotune_load(str(path)) == rp.RPCA_OK
         assert rp.tuning_choices() == before
