@@ -82,6 +82,7 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   const bool warm = kd > 0;
   const int nup = n * (n + 1) / 2;
   const int nfull = n * n;
+  const int n4 = (n + 3) & ~3;  // dot products stop here: entries past n are zero
 
   // Owned entries: upper-triangle (i <= j, column-packed) and full (row-major).
   int ui[MU], uj[MU], fr[MF], fc[MF];
@@ -127,7 +128,7 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   {
     const int nblk = gram_blocks((n + 3) >> 2);
     const int nent = kScalars + nblk * 16;
-    constexpr int kChunk = 16;
+    constexpr int kChunk = 32;  // one batch of loads for up to 32 groups
     for (int idx = tid; idx < nent; idx += NT) {
       double sum = 0.0;
       for (int q0 = 0; q0 < d.groups; q0 += kChunk) {
@@ -179,27 +180,27 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
       int j = 0;
       while ((j + 1) * (j + 2) / 2 <= idx) ++j;
       const int i = idx - j * (j + 1) / 2;
-      const double c = dot4<NMAX>([&](int k, double acc) { return fma(V0s[k * LD + i], V0s[k * LD + j], acc); });
+      const double c = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V0s[k * LD + i], V0s[k * LD + j], acc); });
       G1s[i * LD + j] = c;
       G1s[j * LD + i] = c;
     }
     __syncthreads();
     for (int idx = tid; idx < nfull; idx += NT) {  // V1 = 1.5 V - 0.5 V C  -> V1s
       const int i = idx / n, j = idx - (idx / n) * n;
-      const double vc = dot4<NMAX>([&](int k, double acc) { return fma(V0s[i * LD + k], G1s[k * LD + j], acc); });
+      const double vc = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V0s[i * LD + k], G1s[k * LD + j], acc); });
       V1s[i * LD + j] = fma(-0.5, vc, 1.5 * V0s[i * LD + j]);
     }
     __syncthreads();
     for (int idx = tid; idx < nfull; idx += NT) {  // W = G V1  -> V0s (V is dead)
       const int i = idx / n, j = idx - (idx / n) * n;
-      V0s[i * LD + j] = dot4<NMAX>([&](int k, double acc) { return fma(G0s[i * LD + k], V1s[k * LD + j], acc); });
+      V0s[i * LD + j] = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(G0s[i * LD + k], V1s[k * LD + j], acc); });
     }
     __syncthreads();
     for (int idx = tid; idx < nup; idx += NT) {  // G~ = V1^T W  -> G1s (C is dead)
       int j = 0;
       while ((j + 1) * (j + 2) / 2 <= idx) ++j;
       const int i = idx - j * (j + 1) / 2;
-      const double g = dot4<NMAX>([&](int k, double acc) { return fma(V1s[k * LD + i], V0s[k * LD + j], acc); });
+      const double g = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V1s[k * LD + i], V0s[k * LD + j], acc); });
       G1s[i * LD + j] = g;
       G1s[j * LD + i] = g;
     }
@@ -301,7 +302,7 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
     const int i = idx - j * (j + 1) / 2;
     double s = 0.0;
     if (j < n) {
-      s = dot4<NMAX>([&](int k, double acc) { return fma(Vf[i * LD + k] * w[k], Vf[j * LD + k], acc); });
+      s = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(Vf[i * LD + k] * w[k], Vf[j * LD + k], acc); });
     }
     Pd[i * nb + j] = static_cast<T>(s);
     Pd[j * nb + i] = static_cast<T>(s);

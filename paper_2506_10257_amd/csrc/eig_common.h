@@ -139,6 +139,22 @@ __device__ inline double dot4(F&& term) {
   return (s0 + s1) + (s2 + s3);
 }
 
+// The same sum over the first len terms only (len a multiple of 4, at most
+// NMAX): used where the terms past the matrix size n are exact zeros, so the
+// value is the same and the padding costs nothing.
+template <int NMAX, typename F>
+__device__ inline double dot4n(int len, F&& term) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < len; k += 4) {
+    s0 = term(k + 0, s0);
+    s1 = term(k + 1, s1);
+    s2 = term(k + 2, s2);
+    s3 = term(k + 3, s3);
+  }
+  return (s0 + s1) + (s2 + s3);
+}
+
 // Control step of an eigensolve launch, run by one thread after the
 // reduction has put the pass's scalars in scal (r2, sum|X|, sum X^2,
 // non-finite count).  At the first step it records the norms of X and fixes
