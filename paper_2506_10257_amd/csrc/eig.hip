@@ -55,6 +55,7 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   __shared__ double w[NMAX];
   __shared__ double scal[kScalars];
   __shared__ int s_go;
+  __shared__ double s_tau;
 
   const int tid = threadIdx.x;
   const SolveDesc& d = descs[ids[blockIdx.x]];
@@ -79,6 +80,12 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   const int n = d.n;
   const int nb = d.nb;
   const int kd = st->iter;
+  // read now (thread 0 runs the control step), in flight during the reduction
+  double pf_nXF2 = 0.0, pf_tau = 0.0;
+  if (tid == 0) {
+    pf_nXF2 = st->nXF2;
+    pf_tau = st->tau;
+  }
   const bool warm = kd > 0;
   const int nup = n * (n + 1) / 2;
   const int nfull = n * n;
@@ -164,13 +171,15 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
 
   // 1. Control.
   if (tid == 0) {
-    const int go = eigk::control_step(d, st, scal, kd);
+    double t = 0.0;
+    const int go = eigk::control_step(d, st, scal, kd, pf_nXF2, pf_tau, t);
     s_go = go;
+    s_tau = t;
   }
   __syncthreads();
   if (!s_go) return;
   EIG_MARK(0);
-  const double tau = st->tau;
+  const double tau = s_tau;
   int cur = 0;  // which copy (0 or 1) holds the current G and V
 
   // 2. Warm start.  Each product goes straight into a buffer that is not one

@@ -162,9 +162,14 @@ __device__ inline double dot4n(int len, F&& term) {
 // pass that just ran, ||X - L - S||_F < tol ||X||_F, and the iteration cap.
 // A solve with a given start (S0, Y0) stops after fixing mu (the Gram of its
 // first iterate needs mu) and eigensolves at its next launch.
+// nXF2_prev and tau_prev are the state's ||X||_F^2 and tau as the previous
+// launch left them (read early by the caller); tau_out receives this launch's
+// threshold tau = 1/mu.
 // Returns 1 when the eigensolve of this launch goes ahead.
-__device__ inline int control_step(const SolveDesc& d, SolveState* st, const double* scal, int kd) {
+__device__ inline int control_step(const SolveDesc& d, SolveState* st, const double* scal, int kd,
+                                   double nXF2_prev, double tau_prev, double& tau_out) {
   int go = 0;
+  tau_out = tau_prev;
   if (kd == 0 && d.warm && st->warm_stage == 1) {
     // given start: the reduced Gram is that of A_1 = X - S0 + Y0/mu (the
     // norms and mu were fixed by the previous launch)
@@ -191,6 +196,7 @@ __device__ inline int control_step(const SolveDesc& d, SolveState* st, const dou
       st->mu = mu;
       st->imu = 1.0 / mu;
       st->tau = 1.0 / mu;
+      tau_out = 1.0 / mu;
       st->lam = lam;
       st->gamma = lam / mu;
       // a given start needs one more pass for the Gram of A_1 before the
@@ -200,7 +206,7 @@ __device__ inline int control_step(const SolveDesc& d, SolveState* st, const dou
     }
   } else {
     st->r2 = scal[0];
-    const double rel = sqrt(st->r2) / sqrt(st->nXF2);
+    const double rel = sqrt(scal[0]) / sqrt(nXF2_prev);
     st->resid = rel;
     if (!__builtin_isfinite(st->r2)) {
       st->status = kErrNonfinite;

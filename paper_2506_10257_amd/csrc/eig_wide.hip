@@ -60,6 +60,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   __shared__ double w[NMAX];
   __shared__ double scal[kScalars];
   __shared__ int s_go;
+  __shared__ double s_tau;
 
   const int tid = threadIdx.x;
   const SolveDesc& d = descs[ids[blockIdx.x]];
@@ -68,6 +69,12 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   const int n = d.n;
   const int nb = d.nb;
   const int kd = st->iter;
+  // read now (thread 0 runs the control step), in flight during the reduction
+  double pf_nXF2 = 0.0, pf_tau = 0.0;
+  if (tid == 0) {
+    pf_nXF2 = st->nXF2;
+    pf_tau = st->tau;
+  }
 
   const bool warm = kd > 0;
   // V rows: LDS (stride LDV) or the solve's V buffer (stride nb, nb x nb,
@@ -125,10 +132,14 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   }
   __syncthreads();
 
-  if (tid == 0) s_go = control_step(d, st, scal, kd);
+  if (tid == 0) {
+    double t = 0.0;
+    s_go = control_step(d, st, scal, kd, pf_nXF2, pf_tau, t);
+    s_tau = t;
+  }
   __syncthreads();
   if (!s_go) return;
-  const double tau = st->tau;
+  const double tau = s_tau;
 
   if (warm) {
     // W = G V (every 16 x 16 block) into the scratch buffer, then the upper
