@@ -11,11 +11,12 @@
 //   1. control: decide whether the solve continues (stopping test of the
 //      previous pass, iteration cap, mu and lambda at the first iteration);
 //   2. warm start: G~ = V_prev^T G V_prev with the previous eigenvectors,
-//      which is nearly diagonal once the iteration settles.  V_prev is first
-//      brought back to orthogonality by one Newton-Schulz step of the polar
-//      iteration, V <- V (3I - V^T V) / 2: without it the rounding of the
-//      rotations accumulates over hundreds of iterations and the projector
-//      drifts away from an orthogonal one;
+//      which is nearly diagonal once the iteration settles.  For FP64 solves
+//      V_prev is first brought back to orthogonality by one Newton-Schulz
+//      step of the polar iteration, V <- V (3I - V^T V) / 2: without it the
+//      rounding of the rotations accumulates over hundreds of iterations and
+//      the projector drifts away from an orthogonal one at the 1e-12 level,
+//      which matters for FP64 data but not for FP32 data;
 //   3. cyclic two-sided Jacobi in LDS with the round-robin parallel ordering
 //      (each index meets every other once per sweep, n/2 disjoint pairs per
 //      round).  G and V are double-buffered: a round reads one copy and
@@ -183,37 +184,58 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   int cur = 0;  // which copy (0 or 1) holds the current G and V
 
   // 2. Warm start.  Each product goes straight into a buffer that is not one
-  // of its operands; a barrier separates the products.  G~ and V1 end in copy 1.
+  // of its operands; a barrier separates the products.  FP64 solves first
+  // re-orthonormalise V by one Newton-Schulz step (G~ and V1 end in copy 1);
+  // for FP32 solves the rotations' rounding drift (about 1e-12 over a
+  // thousand steps) stays far below the data's rounding, so G~ = V^T G V is
+  // formed directly (G~ and V end in copy 0).
   if (warm) {
-    for (int idx = tid; idx < nup; idx += NT) {  // C = V^T V  -> G1s
-      int j = 0;
-      while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-      const int i = idx - j * (j + 1) / 2;
-      const double c = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V0s[k * LD + i], V0s[k * LD + j], acc); });
-      G1s[i * LD + j] = c;
-      G1s[j * LD + i] = c;
+    if constexpr (std::is_same<T, double>::value) {
+      for (int idx = tid; idx < nup; idx += NT) {  // C = V^T V  -> G1s
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+        const int i = idx - j * (j + 1) / 2;
+        const double c = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V0s[k * LD + i], V0s[k * LD + j], acc); });
+        G1s[i * LD + j] = c;
+        G1s[j * LD + i] = c;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < nfull; idx += NT) {  // V1 = 1.5 V - 0.5 V C  -> V1s
+        const int i = idx / n, j = idx - (idx / n) * n;
+        const double vc = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V0s[i * LD + k], G1s[k * LD + j], acc); });
+        V1s[i * LD + j] = fma(-0.5, vc, 1.5 * V0s[i * LD + j]);
+      }
+      __syncthreads();
+      for (int idx = tid; idx < nfull; idx += NT) {  // W = G V1  -> V0s (V is dead)
+        const int i = idx / n, j = idx - (idx / n) * n;
+        V0s[i * LD + j] = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(G0s[i * LD + k], V1s[k * LD + j], acc); });
+      }
+      __syncthreads();
+      for (int idx = tid; idx < nup; idx += NT) {  // G~ = V1^T W  -> G1s (C is dead)
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+        const int i = idx - j * (j + 1) / 2;
+        const double g = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V1s[k * LD + i], V0s[k * LD + j], acc); });
+        G1s[i * LD + j] = g;
+        G1s[j * LD + i] = g;
+      }
+      cur = 1;
+    } else {
+      for (int idx = tid; idx < nfull; idx += NT) {  // W = G V  -> G1s
+        const int i = idx / n, j = idx - (idx / n) * n;
+        G1s[i * LD + j] = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(G0s[i * LD + k], V0s[k * LD + j], acc); });
+      }
+      __syncthreads();
+      for (int idx = tid; idx < nup; idx += NT) {  // G~ = V^T W  -> G0s (G is dead)
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= idx) ++j;
+        const int i = idx - j * (j + 1) / 2;
+        const double g = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V0s[k * LD + i], G1s[k * LD + j], acc); });
+        G0s[i * LD + j] = g;
+        G0s[j * LD + i] = g;
+      }
+      cur = 0;
     }
-    __syncthreads();
-    for (int idx = tid; idx < nfull; idx += NT) {  // V1 = 1.5 V - 0.5 V C  -> V1s
-      const int i = idx / n, j = idx - (idx / n) * n;
-      const double vc = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V0s[i * LD + k], G1s[k * LD + j], acc); });
-      V1s[i * LD + j] = fma(-0.5, vc, 1.5 * V0s[i * LD + j]);
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nfull; idx += NT) {  // W = G V1  -> V0s (V is dead)
-      const int i = idx / n, j = idx - (idx / n) * n;
-      V0s[i * LD + j] = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(G0s[i * LD + k], V1s[k * LD + j], acc); });
-    }
-    __syncthreads();
-    for (int idx = tid; idx < nup; idx += NT) {  // G~ = V1^T W  -> G1s (C is dead)
-      int j = 0;
-      while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-      const int i = idx - j * (j + 1) / 2;
-      const double g = dot4n<NMAX>(n4, [&](int k, double acc) { return fma(V1s[k * LD + i], V0s[k * LD + j], acc); });
-      G1s[i * LD + j] = g;
-      G1s[j * LD + i] = g;
-    }
-    cur = 1;
     __syncthreads();
   }
   EIG_MARK(1);
