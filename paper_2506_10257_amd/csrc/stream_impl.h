@@ -52,6 +52,53 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// The value held by the partner lane in an aligned quad of lanes, for a DPP
+// quad permutation CTRL.  Every lane of the wave must be active.
+constexpr int kQuadXor1 = 0xB1;  // lanes [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;  // lanes [2,3,0,1]
+template <int CTRL>
+__device__ inline double quad_swap(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(b)), CTRL,
+                                             0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned>(b >> 32)),
+                                             CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                        static_cast<unsigned>(lo));
+}
+
+// Row chunks per 4x4 Gram block for nblk blocks: as many as the workgroup's
+// threads give (at most 64), lowered to a multiple of 4 (else of 2) where
+// that leaves the longest per-thread row loop as it is, so that aligned lane
+// quads (pairs) can add their block sums in registers.
+__host__ __device__ inline constexpr int gram_chunks(int nblk) {
+  int c = kThreads / nblk;
+  if (c > 64) c = 64;
+  const int rows = (kTile + c - 1) / c;
+  const int c4 = c & ~3, c2 = c & ~1;
+  if (c4 > 0 && (kTile + c4 - 1) / c4 == rows) return c4;
+  if (c2 > 0 && (kTile + c2 - 1) / c2 == rows) return c2;
+  return c;
+}
+__host__ __device__ inline constexpr int gram_lane_group(int c) {
+  return (c & 3) == 0 ? 4 : (c & 1) == 0 ? 2 : 1;
+}
+// LDS stride of one lane-group sum (16 doubles): 144 B keeps each entry
+// 16 B aligned for b128 writes and puts the entries of consecutive writer
+// lanes on different LDS banks.
+constexpr int kRedLd = 18;
+// LDS doubles that the lane-group sums of any frame count up to nb take.
+constexpr int gram_red_doubles(int nb) {
+  int most = 0;
+  for (int n = 1; n <= nb; ++n) {
+    const int nblk = gram_blocks((n + 3) >> 2);
+    const int c = gram_chunks(nblk);
+    const int need = nblk * (c / gram_lane_group(c)) * kRedLd;
+    if (need > most) most = need;
+  }
+  return most;
+}
+
 __device__ inline float clamp_sym(float v, float g) { return fminf(fmaxf(v, -g), g); }
 __device__ inline double clamp_sym(double v, double g) { return fmin(fmax(v, -g), g); }
 __device__ inline bool finite_val(float v) { return __builtin_isfinite(v); }
@@ -65,7 +112,7 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   constexpr int NB4 = (NB + 3) / 4 * 4;
   constexpr int LDT = kTile + 1;  // odd row stride: frames of one row fall in different banks
   constexpr size_t kTileBytes = sizeof(T) * NB4 * LDT;
-  constexpr size_t kRedBytes = sizeof(double) * kThreads * 8;  // half a 4x4 block per pass
+  constexpr size_t kRedBytes = sizeof(double) * gram_red_doubles(NB);
   constexpr size_t kSmem = kTileBytes > kRedBytes ? kTileBytes : kRedBytes;
   __shared__ __align__(16) unsigned char smem[kSmem];
   __shared__ double wred[kThreads / 64][kScalars];
@@ -101,9 +148,12 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
     gam = static_cast<T>(st->gamma);
   }
 
-  // Gram work split: 4x4 blocks of frames x row chunks.
+  // Gram work split: 4x4 blocks of frames x C row chunks; aligned groups of
+  // G lanes (chunks of one block) add in registers, leaving Q sums per block.
   const int nblk = gram_blocks((n + 3) >> 2);
-  const int C = kThreads / nblk;
+  const int C = gram_chunks(nblk);
+  const int G = gram_lane_group(C);
+  const int Q = C / G;
   const int gblk = tid / C;
   const int gc = tid - gblk * C;
   const bool gact = gblk < nblk;
@@ -218,8 +268,9 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
 #ifdef RPCA_TRACE
   const int64_t t_tiles = RPCA_NOW();
 #endif
-  // Workgroup partial: scalars by wave shuffles then waves in order; Gram
-  // blocks by chunk in order.
+  // Workgroup partial.  Scalars: wave shuffles, then the waves in order.
+  // Gram blocks: lane-group sums in registers, then through LDS, where one
+  // thread per block entry adds the Q group sums in chunk order.
   double sc[kScalars] = {r2, s1, s2, nf};
 #pragma unroll
   for (int s = 0; s < kScalars; ++s) sc[s] = wave_sum(sc[s]);
@@ -227,21 +278,28 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
 #pragma unroll
     for (int s = 0; s < kScalars; ++s) wred[tid >> 6][s] = sc[s];
   }
-  double* part = d.partials + static_cast<size_t>(wi.slot) * d.pstride;
+  if (G >= 2) {
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    if (gact) {
+    for (int e = 0; e < 16; ++e) gacc[e] += quad_swap<kQuadXor1>(gacc[e]);
+    if (G == 4) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) red[(gblk * C + gc) * 8 + e] = gacc[half * 8 + e];
+      for (int e = 0; e < 16; ++e) gacc[e] += quad_swap<kQuadXor2>(gacc[e]);
     }
-    __syncthreads();
-    for (int idx = tid; idx < nblk * 8; idx += kThreads) {
-      const int blk = idx >> 3, e = idx & 7;
-      double s = 0.0;
-      for (int c = 0; c < C; ++c) s += red[(blk * C + c) * 8 + e];
-      part[kScalars + blk * 16 + half * 8 + e] = s;
-    }
-    __syncthreads();
+  }
+  if (gact && (gc & (G - 1)) == 0) {
+    double* dst = red + (gblk * Q + gc / G) * kRedLd;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) dst[e] = gacc[e];
+  }
+  __syncthreads();
+  const gptr<double> part = as_global<double>(static_cast<void*>(
+      d.partials + static_cast<size_t>(wi.slot) * d.pstride));
+  for (int idx = tid; idx < nblk * 16; idx += kThreads) {
+    const double* src = red + (idx >> 4) * Q * kRedLd + (idx & 15);
+    double s = 0.0;
+#pragma unroll 4
+    for (int c = 0; c < Q; ++c) s += src[c * kRedLd];
+    part[kScalars + idx] = s;
   }
   if (tid < kScalars) {
     double s = wred[0][tid];
