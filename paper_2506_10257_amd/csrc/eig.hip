@@ -30,8 +30,8 @@
 // with one division: t = sgn(d) 2 g_pq / (|d| + sqrt(d^2 + 4 g_pq^2)),
 // d = g_qq - g_pp, c = 1/sqrt(1 + t^2), s = t c.  A pair is rotated while
 // g_pq^2 > eps^2 |g_pp g_qq| (relative off-diagonal test); eps is 1e-15 for
-// FP64 solves and 1e-9 for FP32 solves, whose Gram entries carry the data's
-// 6e-8 rounding (60x above the off-diagonals left unrotated).
+// FP64 solves and 1e-8 for FP32 solves, whose Gram entries carry the data's
+// 6e-8 rounding (6x above the off-diagonals left unrotated).
 #include <atomic>
 #include <type_traits>
 

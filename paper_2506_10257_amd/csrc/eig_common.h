@@ -19,7 +19,7 @@ struct RotEps<double> {
 };
 template <>
 struct RotEps<float> {
-  static constexpr double eps2 = 1.0e-18;
+  static constexpr double eps2 = 1.0e-16;
 };
 
 template <typename T>
