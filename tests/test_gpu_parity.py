@@ -118,6 +118,26 @@ def test_shapes_fp32(m, n):
     _compare(f"shape {m}x{n}", X, np.float32, ref, None, tol=1e-6, maxit=300)
 
 
+# The FP32 register kernel at frame counts whose Gram blocks split the tile's
+# rows into an odd number of chunks (27, 45), into pairs (50, 60) and into one
+# chunk per block (63): each way of adding the chunk sums inside a workgroup.
+# By default these frame classes run the tile kernel, so the register kernel
+# is selected here.
+@pytest.mark.parametrize("m,n,cls", [(1500, 27, 28), (1300, 45, 48), (1100, 50, 56),
+                                     (1000, 60, 60), (900, 63, 64)])
+def test_register_kernel_fp32_wide_classes(m, n, cls):
+    import paper_2506_10257_amd as rp
+    X = _planted(m, n, 300 + m + n).astype(np.float32)
+    ref = rpca(X.astype(np.float64), tol=1e-6, maxit=300)
+    K = rp.RPCA_KNOB_STREAM_KERNEL
+    old = rp.rpca_tune_get(K, rp.RPCA_F32, cls)
+    assert rp.rpca_tune_set(K, rp.RPCA_F32, cls, 0) == rp.RPCA_OK
+    try:
+        _compare(f"register kernel {m}x{n}", X, np.float32, ref, None, tol=1e-6, maxit=300)
+    finally:
+        rp.rpca_tune_set(K, rp.RPCA_F32, cls, old)
+
+
 # ------------------------------------------------------------ special cases
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 def test_zero_input(dtype):
