@@ -71,16 +71,18 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(X, lam, budget_s: float = 12.0, max_iters: int = 40):
+def cpu_baseline(X, lam, budget_s: float = 12.0, max_iters: int = 40, one_thread_iters: int = 3):
     """FP64 oracle on this host: iterations of the same window until the
-    budget is used (tol = 0 runs a fixed count)."""
+    budget is used (tol = 0 runs a fixed count) with the BLAS pool as it is,
+    then a few iterations with the pool limited to one thread."""
     import numpy as np
     from oracle import rpca
-    threads = None
+    threads, limits = None, None
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         info = threadpool_info()
         threads = max((d.get("num_threads") or 0) for d in info) if info else None
+        limits = threadpool_limits
     except Exception:
         pass
     m, n = X.shape
@@ -92,10 +94,18 @@ def cpu_baseline(X, lam, budget_s: float = 12.0, max_iters: int = 40):
     t0 = time.perf_counter()
     rpca(X64, lam=lam, tol=0.0, maxit=iters)
     dt = time.perf_counter() - t0
-    return {"value": m * n * iters / dt, "unit": "pixel-frames/s per ALM iter",
-            "cores": threads or len(os.sched_getaffinity(0)), "kind": "oracle",
-            "sample": f"{iters} FP64 ALM iterations (full SVD) of the {m}x{n} window, tol=0",
-            "host_cpus": len(os.sched_getaffinity(0))}
+    out = {"value": m * n * iters / dt, "unit": "pixel-frames/s per ALM iter",
+           "cores": threads or len(os.sched_getaffinity(0)), "kind": "oracle",
+           "sample": f"{iters} FP64 ALM iterations (full SVD) of the {m}x{n} window, tol=0",
+           "s_per_iter": dt / iters, "host_cpus": len(os.sched_getaffinity(0))}
+    if limits is not None and one_thread_iters > 0:
+        with limits(limits=1):
+            t0 = time.perf_counter()
+            rpca(X64, lam=lam, tol=0.0, maxit=one_thread_iters)
+            d1 = time.perf_counter() - t0
+        out["one_thread"] = {"value": m * n * one_thread_iters / d1, "iters": one_thread_iters,
+                             "s_per_iter": d1 / one_thread_iters}
+    return out
 
 
 def _gen_batch_window(args):

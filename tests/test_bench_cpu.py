@@ -62,7 +62,8 @@ def test_committed_traffic_summary_is_well_formed():
 def test_cpu_baseline_record():
     rng = np.random.default_rng(0)
     X = rng.standard_normal((300, 6))
-    rec = bench.cpu_baseline(X, 1.0 / np.sqrt(300), budget_s=0.2, max_iters=3)
+    rec = bench.cpu_baseline(X, 1.0 / np.sqrt(300), budget_s=0.2, max_iters=3, one_thread_iters=2)
     assert rec["kind"] == "oracle" and rec["unit"] == "pixel-frames/s per ALM iter"
-    assert rec["value"] > 0 and rec["cores"] >= 1
+    assert rec["value"] > 0 and rec["cores"] >= 1 and rec["s_per_iter"] > 0
     assert "300x6" in rec["sample"]
+    assert rec["one_thread"]["iters"] == 2 and rec["one_thread"]["value"] > 0
