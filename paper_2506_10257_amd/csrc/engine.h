@@ -122,7 +122,9 @@ void assign_lanes(std::vector<SolveRec*>& recs, int nlanes);
 // Memory pool of the device: keep freed blocks cached (set once per device).
 void setup_pool(int dev);
 bool graphs_disabled();
-constexpr int kMaxLanes = 3;
+// Streams a plan's solves are spread over: the hardware queues a process
+// gets by default (4).
+constexpr int kMaxLanes = 4;
 
 void set_error(const char* what, hipError_t e);
 void set_error_text(const char* text);
