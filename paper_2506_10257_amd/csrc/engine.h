@@ -125,6 +125,10 @@ bool graphs_disabled();
 // Streams a plan's solves are spread over: the hardware queues a process
 // gets by default (4).
 constexpr int kMaxLanes = 4;
+// The server's plans mix solves at every stage of their iterations; six
+// streams (two of them sharing hardware queues) keep more eigensolves in
+// flight beside the streaming passes there.
+constexpr int kServeLanes = 6;
 
 void set_error(const char* what, hipError_t e);
 void set_error_text(const char* text);

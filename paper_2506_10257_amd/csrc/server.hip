@@ -137,7 +137,7 @@ std::vector<SolveRec*> recs_of(const std::vector<Req*>& v) {
   return out;
 }
 
-int nlanes_for(size_t count) { return static_cast<int>(std::min<size_t>(count, kMaxLanes)); }
+int nlanes_for(size_t count) { return static_cast<int>(std::min<size_t>(count, kServeLanes)); }
 
 // Fork the lanes from lane 0 (each lane waits for lane 0's work so far).
 hipError_t fork_from0(const Lanes& L) {
@@ -158,7 +158,7 @@ hipError_t join_to0(const Lanes& L) {
 
 int step_device(rpca_server* s) {
   if (!s->lanes_ok) {
-    const int rc = lanes_create(s->lanes, kMaxLanes);
+    const int rc = lanes_create(s->lanes, kServeLanes);
     if (rc != RPCA_OK) return rc;
     s->lanes_ok = true;
   }
