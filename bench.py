@@ -114,10 +114,12 @@ def _gen_batch_window(args):
     return batch_window(H, W, n, seed).X().astype("float32")
 
 
-def run_batch(args):
-    """64 uneven windows (sizes {256^2, 384x512, 512^2, 512x768} x frames
-    {10, 20, 40, 60}) solved together by rpca_solve_many, against the plain
-    path that solves them one call at a time."""
+def batch_measure(count: int, steps: int, warmup: int) -> dict:
+    """The 64-window batch (sizes {256^2, 384x512, 512^2, 512x768} x frames
+    {10, 20, 40, 60}, FP32, tol 1e-6, maxit 1000) solved together by
+    rpca_solve_many, against the plain path that solves the same windows one
+    call at a time.  Returns the figures of the batched path (throughput,
+    solves/s, per-iteration HBM fraction, kernel split) and of the plain path."""
     import numpy as np
     import torch
     from concurrent.futures import ProcessPoolExecutor
@@ -126,20 +128,22 @@ def run_batch(args):
     from synth import batch_shapes
 
     dev = torch.device("cuda:0")
-    shapes = batch_shapes(args.count)
+    shapes = batch_shapes(count)
     workers = min(16, len(os.sched_getaffinity(0)))
     with ProcessPoolExecutor(workers) as ex:
         Xs = list(ex.map(_gen_batch_window, shapes))
     Ms = [torch.from_numpy(np.ascontiguousarray(X.T)).to(dev).t() for X in Xs]
     elems = [X.shape[0] * X.shape[1] for X in Xs]
+    del Xs
     tol, maxit = 1e-6, 1000
     torch.cuda.synchronize()
+    print(f"[batch] {len(Ms)} windows, {sum(elems) / 1e6:.0f} M elements", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         rp.solve_many(Ms, tol=tol, maxit=maxit)
     torch.cuda.synchronize()
     walls, work = [], 0
-    for _ in range(args.steps):
+    for _ in range(steps):
         t0 = time.perf_counter()
         res = rp.solve_many(Ms, tol=tol, maxit=maxit)
         torch.cuda.synchronize()
@@ -158,6 +162,7 @@ def run_batch(args):
     timed_wall = time.perf_counter() - t0
     rp.rpca_profile_enable(False)
     prof = rp.rpca_profile_read(reset=True)
+    print(f"[batch] batched: {len(Ms) * steps / wall:.2f} solves/s", file=sys.stderr, flush=True)
 
     # plain path: one solve per call, in order
     t0 = time.perf_counter()
@@ -170,37 +175,92 @@ def run_batch(args):
         plain_work += e * r.iterations
     plain_wall = plain_done[-1]
     achieved = prof["update_bytes"] / (prof["update_ms"] * 1e-3) / 1e9 if prof["update_ms"] > 0 else 0.0
-    out = {
-        "metric": METRIC,
-        "value": work / wall,
-        "unit": "pixel-frames/s per ALM iter",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (64 seeded ultrasound-shaped windows, density 1 bound + 2 free "
-                "bubbles per 1300 px^2)",
-        "config": {"workload": "rpca_batch64_uneven", "count": len(Ms), "tol": tol, "maxit": maxit,
-                   "elements": int(sum(elems)), "iterations_min": int(min(iters)),
-                   "iterations_max": int(max(iters)), "iterations_mean": float(np.mean(iters))},
-        "solves_per_s": len(Ms) * args.steps / wall,
+    value = work / wall
+    return {
+        "workload": "rpca_batch64_uneven", "count": len(Ms), "steps": steps, "warmup": warmup,
+        "tol": tol, "maxit": maxit, "elements": int(sum(elems)),
+        "iterations_min": int(min(iters)), "iterations_max": int(max(iters)),
+        "iterations_mean": float(np.mean(iters)),
+        "value": value, "unit": "pixel-frames/s per ALM iter",
+        "ms_per_step": wall / steps * 1e3,
+        "solves_per_s": len(Ms) * steps / wall,
+        # 5 FP32 words per entry and iteration (read X, S, Y; write S, Y) over wall time
+        "per_iteration_frac": value * 20.0 / (HBM_PEAK_GBS * 1e9),
+        "update_kernels": {"achieved_GBps": achieved, "frac": achieved / HBM_PEAK_GBS,
+                           "launches": prof["update_launches"],
+                           "measured_on": "one extra step, each launch recording its own HIP "
+                                          "start/stop event pair (one stream)"},
         "latency_ms": {"p50": float(np.percentile(walls, 50)) * 1e3,
                        "p99": float(np.percentile(walls, 99)) * 1e3},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "update pass, all frame classes (k_wide MFMA tile kernel for the "
-                               "classes in tuning.tile_kernel_classes, k_stream register kernel "
-                               "for the others)",
-                     "launches": prof["update_launches"],
-                     "measured_on": "one extra step, each launch recording its own HIP "
-                                    "start/stop event pair (one stream)"},
-        "tuning": tuning_summary(),
         "kernel_timed_step": {"ms": timed_wall * 1e3,
                               **{k: prof[k] for k in ("init_ms", "eig_ms", "update_ms", "finalize_ms")}},
         "plain": {"value": plain_work / plain_wall, "solves_per_s": len(Ms) / plain_wall,
+                  "per_iteration_frac": plain_work / plain_wall * 20.0 / (HBM_PEAK_GBS * 1e9),
                   "latency_ms": {"p50": float(np.percentile(plain_done, 50)) * 1e3,
                                  "p99": float(np.percentile(plain_done, 99)) * 1e3}},
     }
+
+
+def run_batch(args):
+    """The 64-window batch as its own bench line."""
+    b = batch_measure(args.count, args.steps, args.warmup)
+    out = {
+        "metric": METRIC,
+        "value": b["value"],
+        "unit": "pixel-frames/s per ALM iter",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": b["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (64 seeded ultrasound-shaped windows, density 1 bound + 2 free "
+                "bubbles per 1300 px^2)",
+        "config": {k: b[k] for k in ("workload", "count", "tol", "maxit", "elements",
+                                     "iterations_min", "iterations_max", "iterations_mean")},
+        "solves_per_s": b["solves_per_s"],
+        "latency_ms": b["latency_ms"],
+        "roofline": {"bound": "hbm", "achieved": b["update_kernels"]["achieved_GBps"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": b["update_kernels"]["frac"],
+                     "per_iteration_frac": b["per_iteration_frac"], "traffic": None,
+                     "kernel": "update pass, all frame classes (k_wide MFMA tile kernel for the "
+                               "classes in tuning.tile_kernel_classes, k_stream register kernel "
+                               "for the others)",
+                     "launches": b["update_kernels"]["launches"],
+                     "measured_on": b["update_kernels"]["measured_on"]},
+        "tuning": tuning_summary(),
+        "kernel_timed_step": b["kernel_timed_step"],
+        "plain": b["plain"],
+    }
     print(json.dumps(out), flush=True)
+
+
+def latency_128x128x20_f64(solves: int = 20) -> dict:
+    """The latency workload: one FP64 solve of the seeded 128x128 x 20 window
+    (lambda 1/128, tol 1e-7, maxit 500) per call, p50/p99 of the call time."""
+    import numpy as np
+    import torch
+
+    import paper_2506_10257_amd as rp
+    from synth import window_128x128x20
+
+    X = window_128x128x20().X()
+    m, n = X.shape
+    M = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda:0").t()
+    kw = dict(lam=1.0 / 128, tol=1e-7, maxit=500)
+    rp.solve(M, **kw)
+    torch.cuda.synchronize()
+    times, its = [], []
+    for _ in range(solves):
+        t0 = time.perf_counter()
+        r = rp.solve(M, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        its.append(r.iterations)
+    it = int(np.median(its))
+    return {"workload": "rpca_128x128x20_f64_latency", "m": m, "n": n, "dtype": "f64", **kw,
+            "solves": solves, "iterations": it, "status": int(r.status),
+            "latency_ms": {"p50": float(np.percentile(times, 50)) * 1e3,
+                           "p99": float(np.percentile(times, 99)) * 1e3},
+            "us_per_iteration": float(np.median(times)) / max(it, 1) * 1e6,
+            "value": m * n * it / float(np.median(times)), "unit": "pixel-frames/s per ALM iter"}
 
 
 def run_serve(args):
@@ -595,6 +655,8 @@ def main():
     ap.add_argument("--quantum", type=int, default=16, help="serve: iterations per step")
     ap.add_argument("--budget-gb", type=float, default=160.0, help="serve: admission budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="single: skip the 128x128x20 FP64 latency and the 64-window batch records")
     ap.add_argument("--maxit132", type=int, default=300, help="frames132: iteration cap")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -698,6 +760,8 @@ def main():
         kname = f"k_stream<{'float' if args.dtype == 'f32' else 'double'},20,kModeUpdate>"
         traffic = measured_traffic() if args.dtype == "f32" else None
     lat = np.array(times) * 1e3
+    wbytes = 4 if args.dtype == "f32" else 8
+    per_iter_gbs = value * 5 * wbytes / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -718,6 +782,10 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     # the whole iteration (eigensolve, update and reduction in
+                     # series): 5 words per entry and iteration over solve wall time
+                     "per_iteration_achieved": per_iter_gbs,
+                     "per_iteration_frac": per_iter_gbs / HBM_PEAK_GBS,
                      "kernel": kname,
                      "bytes_per_launch": bytes_per_launch, "mean_launch_us": upd_ms * 1e3,
                      "launches": prof["update_launches"],
@@ -731,6 +799,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(X, lam)
+    if not args.no_extra:
+        out["latency_128x128x20_f64"] = latency_128x128x20_f64()
+        print(f"[bench] latency workload: {out['latency_128x128x20_f64']['latency_ms']}",
+              file=sys.stderr, flush=True)
+        out["batch"] = batch_measure(64, 3, 1)
     print(json.dumps(out), flush=True)
 
 

@@ -53,6 +53,7 @@ extern "C" {
 #define RPCA_ERR_DEVICE        -3  /* HIP runtime error                      */
 #define RPCA_ERR_NONFINITE     -4  /* NaN or Inf in M (or in the iteration)  */
 #define RPCA_ERR_UNSUPPORTED   -5  /* shape not supported by the library     */
+#define RPCA_ERR_TIMEOUT       -6  /* server: the request's timeout passed   */
 /* Negative codes leave L and S unspecified. */
 
 /* ---- element types and contraction modes -------------------------------- */
@@ -258,12 +259,29 @@ int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls);
  *   rpca_server_pending queued and active counts and the admitted bytes;
  *                       returns the number of requests not yet reported.
  *
+ *   rpca_server_set_timeout  timeout (seconds, > 0; 0 = none, the default)
+ *                       given to the requests submitted from then on.  A
+ *                       request whose timeout has passed since its
+ *                       submission completes with RPCA_ERR_TIMEOUT at the
+ *                       next step: a queued one at once, an active one after
+ *                       the quantum in flight, its workspace freed and its L
+ *                       and S unspecified.  RPCA_ERR_ARG for a negative or
+ *                       NaN value.
+ *
+ * A tag names one request until its completion has been reported: submit
+ * returns RPCA_ERR_ARG for a tag that is queued, active or completed but not
+ * yet reported.  A failure while newly admitted requests are set up
+ * (workspace, control block, init pass) completes those requests with the
+ * failure's code and gives their footprint back to the budget; the step then
+ * returns RPCA_OK, or RPCA_ERR_DEVICE for a device error.
+ *
  * Each result is bitwise identical to the same problem solved alone.  The
  * calls are serialised by a lock; the stream argument of create is the stream
  * on which the caller produces M (it is synchronised before admission).
  * flags: 0, or RPCA_SERVER_SIMULATE to run the admission logic without any
  * device work (every request then completes after maxit iterations with
- * RPCA_NOT_CONVERGED and residual 0).  create returns NULL for an invalid
+ * RPCA_NOT_CONVERGED and residual 0; the server clock of the timeouts then
+ * advances by exactly 1 ms per step).  create returns NULL for an invalid
  * argument (dtype, an unknown gram_mode or a split-BF16 mode with RPCA_F64,
  * a zero budget, max_active < 1, quantum < 1, unknown flags).  Every
  * request of a server uses the server's dtype and gram_mode.
@@ -290,6 +308,13 @@ size_t rpca_server_peak_bytes(rpca_server* s);
 size_t rpca_server_request_bytes(int64_t m, int64_t n, int32_t dtype);
 /* Wait for device work, free every workspace and drop queued requests. */
 void rpca_server_destroy(rpca_server* s);
+int rpca_server_set_timeout(rpca_server* s, double seconds);
+/* Fault injection for tests of the failure handling: the next set-up of newly
+ * admitted requests (stage RPCA_SERVER_STAGE_INIT) fails with `code` (< 0)
+ * before any device work, as a failed workspace or control-block allocation
+ * would.  Returns RPCA_OK, or RPCA_ERR_ARG for another stage or code >= 0. */
+#define RPCA_SERVER_STAGE_INIT 1
+int rpca_server_inject_failure(rpca_server* s, int32_t stage, int32_t code);
 
 /*
  * Autotuning: choose every tuning knob by measurement on the current device.

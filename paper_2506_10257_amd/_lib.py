@@ -18,6 +18,7 @@ RPCA_ERR_NOMEM = -2
 RPCA_ERR_DEVICE = -3
 RPCA_ERR_NONFINITE = -4
 RPCA_ERR_UNSUPPORTED = -5
+RPCA_ERR_TIMEOUT = -6
 RPCA_F64 = 0
 RPCA_F32 = 1
 RPCA_GRAM_DEFAULT = 0
@@ -28,6 +29,7 @@ RPCA_KNOB_EIG_THREADS = 1
 RPCA_KNOB_STREAM_KERNEL = 2
 RPCA_KNOB_TILE_ROWS = 3
 RPCA_SERVER_SIMULATE = 1
+RPCA_SERVER_STAGE_INIT = 1
 
 EXPORTS = (
     "rpca_solve_f64", "rpca_solve_f32", "rpca_solve_many", "rpca_solve_ex",
@@ -36,6 +38,7 @@ EXPORTS = (
     "rpca_tune_set", "rpca_tune_get",
     "rpca_server_create", "rpca_server_submit", "rpca_server_step", "rpca_server_pending",
     "rpca_server_peak_bytes", "rpca_server_request_bytes", "rpca_server_destroy",
+    "rpca_server_set_timeout", "rpca_server_inject_failure",
     "rpca_autotune", "rpca_autotune_save", "rpca_autotune_load",
     "rpca_frame_correlation", "rpca_frame_keep", "rpca_frame_select", "rpca_moving_average",
     "rpca_dice", "rpca_rmse", "rpca_masked_mean",
@@ -145,6 +148,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rpca_server_request_bytes.restype = sz
     lib.rpca_server_destroy.argtypes = [vp]
     lib.rpca_server_destroy.restype = None
+    lib.rpca_server_set_timeout.argtypes = [vp, dbl]
+    lib.rpca_server_set_timeout.restype = ctypes.c_int
+    lib.rpca_server_inject_failure.argtypes = [vp, i32, i32]
+    lib.rpca_server_inject_failure.restype = ctypes.c_int
     lib.rpca_autotune.argtypes = [i32, i64, vp]
     lib.rpca_autotune.restype = ctypes.c_int
     lib.rpca_autotune_save.argtypes = [ctypes.c_char_p]

@@ -969,6 +969,7 @@ const char* rpca_strerror(int code) {
     case RPCA_ERR_DEVICE: return "HIP runtime error";
     case RPCA_ERR_NONFINITE: return "non-finite value in the input or the iteration";
     case RPCA_ERR_UNSUPPORTED: return "shape not supported by the library";
+    case RPCA_ERR_TIMEOUT: return "the request's timeout passed before it finished";
     default: return "unknown status";
   }
 }

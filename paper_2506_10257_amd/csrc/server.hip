@@ -18,12 +18,20 @@
 // A solve's arithmetic depends only on its own data and shape, so its result
 // is bitwise the same whatever else is active.
 //
+// A request may carry a timeout (rpca_server_set_timeout before submitting):
+// once that much time has passed since its submission, it is completed with
+// RPCA_ERR_TIMEOUT at the next step, whether it is still queued or active
+// (an active solve is dropped after the quantum that was running, its
+// workspace freed and its L and S left unspecified).
+//
 // With RPCA_SERVER_SIMULATE no HIP call is made: admission and retirement run
 // as above and every request finishes after maxit iterations, counted in
-// quanta.  This exercises the queueing logic without a device.
+// quanta, on a clock that advances by exactly 1 ms per step.  This exercises
+// the queueing, timeout and failure logic without a device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -45,6 +53,7 @@ struct Req {
   size_t footprint = 0;  // admission footprint
   SolveRec rec;
   int sim_iter = 0;      // simulate: iterations run
+  int64_t deadline = 0;  // server clock (ns) after which it times out; 0 = never
 };
 
 size_t io_bytes(int64_t m, int64_t n, int dtype) {
@@ -69,6 +78,9 @@ struct rpca_server {
   bool lanes_ok = false;
   rpca::Plan plan;
   bool plan_valid = false;
+  double timeout_s = 0.0;   // applied to requests submitted from now on
+  int64_t sim_clock = 0;    // simulate: ns, +1 ms per step
+  int inject_init = 0;      // fail the next init stage with this code (0 = none)
   std::mutex mu;
 };
 
@@ -93,6 +105,47 @@ void complete(rpca_server* s, Req* r, int status, int iters, double resid) {
   s->ready.push_back(c);
 }
 
+// Server clock in ns: steady time, or the simulated clock.
+int64_t now_ns(const rpca_server* s) {
+  if (s->simulate) return s->sim_clock;
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+bool expired(const rpca_server* s, const Req* r, int64_t now) {
+  return r->deadline != 0 && now >= r->deadline;
+}
+
+// Complete every queued request whose deadline has passed.
+void expire_queued(rpca_server* s, int64_t now) {
+  for (auto it = s->queue.begin(); it != s->queue.end();) {
+    if (expired(s, *it, now)) {
+      complete(s, *it, RPCA_ERR_TIMEOUT, 0, 0.0);
+      delete *it;
+      it = s->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+// Newly admitted requests whose set-up failed: give back their workspace
+// (if they got one) and their share of the budget, and complete them with
+// the failure's code.
+void fail_admitted(rpca_server* s, std::vector<Req*>& reqs, int code, hipStream_t stream) {
+  for (Req* r : reqs) {
+    if (r->rec.mem) {
+      (void)hipFreeAsync(r->rec.mem, stream);
+      r->rec.mem = nullptr;
+    }
+    s->used -= r->footprint;
+    complete(s, r, code, 0, 0.0);
+    delete r;
+  }
+  reqs.clear();
+}
+
 // FIFO admission under max_active and the footprint budget.
 void admit(rpca_server* s, std::vector<Req*>& fresh) {
   while (!s->queue.empty() && static_cast<int>(s->active.size() + fresh.size()) < s->max_active) {
@@ -112,13 +165,25 @@ void admit(rpca_server* s, std::vector<Req*>& fresh) {
 }
 
 int step_simulated(rpca_server* s) {
+  s->sim_clock += 1000000;  // 1 ms per step
+  const int64_t now = now_ns(s);
+  expire_queued(s, now);
   std::vector<Req*> fresh;
   admit(s, fresh);
+  if (!fresh.empty() && s->inject_init != 0) {
+    const int code = s->inject_init;
+    s->inject_init = 0;
+    fail_admitted(s, fresh, code, nullptr);
+  }
   for (Req* r : fresh) s->active.push_back(r);
   std::vector<Req*> keep;
   for (Req* r : s->active) {
     r->sim_iter = std::min(r->p.maxit, r->sim_iter + s->quantum);
-    if (r->sim_iter >= r->p.maxit) {
+    if (expired(s, r, now) && r->sim_iter < r->p.maxit) {
+      complete(s, r, RPCA_ERR_TIMEOUT, r->sim_iter, 0.0);
+      s->used -= r->footprint;
+      delete r;
+    } else if (r->sim_iter >= r->p.maxit) {
       complete(s, r, RPCA_NOT_CONVERGED, r->sim_iter, 0.0);
       s->used -= r->footprint;
       delete r;
@@ -156,6 +221,71 @@ hipError_t join_to0(const Lanes& L) {
   return e;
 }
 
+// Set-up of newly admitted requests: workspace, then their init pass.  On a
+// failure the requests of this stage are released (fail_admitted) before the
+// code is returned, so nothing leaks and the budget is given back.
+int start_admitted(rpca_server* s, std::vector<Req*>& fresh) {
+  Lanes& L = s->lanes;
+  hipStream_t s0 = L.s[0];
+  if (s->inject_init != 0) {
+    const int code = s->inject_init;
+    s->inject_init = 0;
+    fail_admitted(s, fresh, code, s0);
+    return code == RPCA_ERR_DEVICE ? code : RPCA_OK;
+  }
+  {
+    const hipError_t e = hipStreamSynchronize(s->user);  // inputs come from the caller's stream
+    if (e != hipSuccess) {
+      set_error("hipStreamSynchronize(caller stream)", e);
+      fail_admitted(s, fresh, RPCA_ERR_DEVICE, s0);
+      return RPCA_ERR_DEVICE;
+    }
+  }
+  std::vector<Req*> ok;
+  for (Req* r : fresh) {
+    void* mem = nullptr;
+    const hipError_t e = hipMallocAsync(&mem, r->rec.big.total, s0);
+    if (e != hipSuccess || mem == nullptr) {
+      (void)hipGetLastError();
+      s->used -= r->footprint;
+      complete(s, r, RPCA_ERR_NOMEM, 0, 0.0);
+      delete r;
+      continue;
+    }
+    r->rec.mem = static_cast<char*>(mem);
+    ok.push_back(r);
+  }
+  fresh.clear();
+  if (ok.empty()) return RPCA_OK;
+  std::vector<SolveRec*> recs = recs_of(ok);
+  const int nl = nlanes_for(recs.size());
+  assign_lanes(recs, nl);
+  Plan pn;
+  const int rc = plan_build(pn, recs, nl, s->dtype, s0);
+  if (rc != RPCA_OK) {
+    plan_free(pn, s0);
+    fail_admitted(s, ok, rc, s0);
+    return rc == RPCA_ERR_DEVICE ? rc : RPCA_OK;
+  }
+  Lanes sub;  // the first nl lanes
+  sub.s.assign(L.s.begin(), L.s.begin() + nl);
+  sub.join.assign(L.join.begin(), L.join.begin() + nl);
+  sub.fork = L.fork;
+  hipError_t e = enqueue_reset_states(pn, s0);
+  if (e == hipSuccess) e = enqueue_init(pn, sub);
+  if (e == hipSuccess) e = join_to0(sub);
+  if (e != hipSuccess) {
+    set_error("server init stage", e);
+    plan_free(pn, s0);
+    fail_admitted(s, ok, RPCA_ERR_DEVICE, s0);
+    return RPCA_ERR_DEVICE;
+  }
+  plan_free(pn, s0);
+  for (Req* r : ok) s->active.push_back(r);
+  s->plan_valid = false;
+  return RPCA_OK;
+}
+
 int step_device(rpca_server* s) {
   if (!s->lanes_ok) {
     const int rc = lanes_create(s->lanes, kServeLanes);
@@ -165,43 +295,14 @@ int step_device(rpca_server* s) {
   Lanes& L = s->lanes;
   hipStream_t s0 = L.s[0];
 
-  // 1-2. admission, workspace and init pass of the newly admitted solves
+  // 1-2. timeouts of queued requests; admission, workspace and init pass of
+  // the newly admitted solves
+  expire_queued(s, now_ns(s));
   std::vector<Req*> fresh;
   admit(s, fresh);
   if (!fresh.empty()) {
-    SV(hipStreamSynchronize(s->user));  // inputs are produced on the caller's stream
-    std::vector<Req*> ok;
-    for (Req* r : fresh) {
-      void* mem = nullptr;
-      const hipError_t e = hipMallocAsync(&mem, r->rec.big.total, s0);
-      if (e != hipSuccess || mem == nullptr) {
-        (void)hipGetLastError();
-        s->used -= r->footprint;
-        complete(s, r, RPCA_ERR_NOMEM, 0, 0.0);
-        delete r;
-        continue;
-      }
-      r->rec.mem = static_cast<char*>(mem);
-      ok.push_back(r);
-    }
-    if (!ok.empty()) {
-      std::vector<SolveRec*> recs = recs_of(ok);
-      const int nl = nlanes_for(recs.size());
-      assign_lanes(recs, nl);
-      Plan pn;
-      int rc = plan_build(pn, recs, nl, s->dtype, s0);
-      if (rc != RPCA_OK) return rc;
-      Lanes sub;  // the first nl lanes
-      sub.s.assign(L.s.begin(), L.s.begin() + nl);
-      sub.join.assign(L.join.begin(), L.join.begin() + nl);
-      sub.fork = L.fork;
-      SV(enqueue_reset_states(pn, s0));
-      SV(enqueue_init(pn, sub));
-      SV(join_to0(sub));
-      plan_free(pn, s0);
-      for (Req* r : ok) s->active.push_back(r);
-      s->plan_valid = false;
-    }
+    const int rc = start_admitted(s, fresh);
+    if (rc != RPCA_OK) return rc;
   }
   if (s->active.empty()) return RPCA_OK;
 
@@ -212,7 +313,7 @@ int step_device(rpca_server* s) {
     std::vector<SolveRec*> recs = recs_of(s->active);
     assign_lanes(recs, nlanes_for(recs.size()));
     const int rc = plan_build(s->plan, recs, nlanes_for(recs.size()), s->dtype, s0);
-    if (rc != RPCA_OK) return rc;
+    if (rc != RPCA_OK) return rc;  // the active solves stay; the next step retries
     s->plan_valid = true;
   }
   const int rcp = lanes_reserve_pinned(L, static_cast<int>(s->active.size()));
@@ -235,16 +336,40 @@ int step_device(rpca_server* s) {
   }
   for (size_t i = 0; i < s->active.size(); ++i) s->active[i]->rec.st = L.pinned[0][i];
 
-  // 4. retire the solves that stopped
-  std::vector<Req*> done, keep;
-  for (Req* r : s->active) (r->rec.st.done ? done : keep).push_back(r);
+  // 4. retire the solves that stopped, and drop those past their deadline
+  const int64_t now = now_ns(s);
+  std::vector<Req*> done, late, keep;
+  for (Req* r : s->active) {
+    if (r->rec.st.done) done.push_back(r);
+    else if (expired(s, r, now)) late.push_back(r);
+    else keep.push_back(r);
+  }
+  if (!late.empty()) {
+    // every lane joined lane 0 in the snapshot, so their work on these
+    // workspaces is ordered before the frees
+    for (Req* r : late) {
+      SV(hipFreeAsync(r->rec.mem, s0));
+      r->rec.mem = nullptr;
+      complete(s, r, RPCA_ERR_TIMEOUT, r->rec.st.iter, r->rec.st.resid);
+      s->used -= r->footprint;
+      delete r;
+    }
+    late.clear();
+    s->plan_valid = false;
+  }
   if (!done.empty()) {
     std::vector<SolveRec*> recs = recs_of(done);
     const int nl = nlanes_for(recs.size());
     assign_lanes(recs, nl);
     Plan pd;
     const int rc = plan_build(pd, recs, nl, s->dtype, s0);
-    if (rc != RPCA_OK) return rc;
+    if (rc != RPCA_OK) {
+      // keep them active (they exit their launches at once); retried next step
+      plan_free(pd, s0);
+      for (Req* r : done) keep.push_back(r);
+      s->active.swap(keep);
+      return rc;
+    }
     Lanes sub;
     sub.s.assign(L.s.begin(), L.s.begin() + nl);
     sub.join.assign(L.join.begin(), L.join.begin() + nl);
@@ -263,9 +388,9 @@ int step_device(rpca_server* s) {
       s->used -= r->footprint;
       delete r;
     }
-    s->active.swap(keep);
     s->plan_valid = false;
   }
+  s->active.swap(keep);
   return RPCA_OK;
 }
 
@@ -325,7 +450,33 @@ int rpca_server_submit(rpca_server* s, const rpca_problem* p, int64_t tag) {
   }
   r->footprint = rpca_server_request_bytes(p->m, p->n, s->dtype);
   std::lock_guard<std::mutex> lk(s->mu);
+  // a tag names one request until its completion has been reported
+  bool dup = false;
+  for (const Req* q : s->queue) dup = dup || q->tag == tag;
+  for (const Req* q : s->active) dup = dup || q->tag == tag;
+  for (const rpca_completion& c : s->ready) dup = dup || c.tag == tag;
+  if (dup) {
+    delete r;
+    set_error_text("rpca_server_submit: tag already in use");
+    return RPCA_ERR_ARG;
+  }
+  if (s->timeout_s > 0.0)
+    r->deadline = now_ns(s) + static_cast<int64_t>(s->timeout_s * 1e9 + 0.5);
   s->queue.push_back(r);
+  return RPCA_OK;
+}
+
+int rpca_server_set_timeout(rpca_server* s, double seconds) {
+  if (!s || !(seconds >= 0.0) || seconds > 1e9) return RPCA_ERR_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->timeout_s = seconds;
+  return RPCA_OK;
+}
+
+int rpca_server_inject_failure(rpca_server* s, int32_t stage, int32_t code) {
+  if (!s || stage != RPCA_SERVER_STAGE_INIT || code >= 0) return RPCA_ERR_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->inject_init = code;
   return RPCA_OK;
 }
 

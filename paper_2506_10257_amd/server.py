@@ -14,7 +14,8 @@ from dataclasses import dataclass
 from typing import Optional
 
 from . import _lib
-from ._lib import RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_SERVER_SIMULATE, RpcaCompletion
+from ._lib import (RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_SERVER_SIMULATE,
+                   RPCA_SERVER_STAGE_INIT, RpcaCompletion)
 
 
 @dataclass
@@ -52,24 +53,50 @@ class Server:
         self._cap = max(int(max_active), 1) * 4
         self._buf = (RpcaCompletion * self._cap)()
         self._live = {}  # tag -> (M, L, S) kept alive until completion
+        self._timeout = 0.0
+
+    def set_timeout(self, seconds: float) -> None:
+        """Timeout given to the requests submitted from now on (0 = none)."""
+        rc = self._lib.rpca_server_set_timeout(self._h, float(seconds))
+        if rc != 0:
+            raise ValueError(f"invalid timeout {seconds!r}")
+        self._timeout = float(seconds)
+
+    def inject_failure(self, code: int, stage: int = RPCA_SERVER_STAGE_INIT) -> int:
+        """Make the next set-up of admitted requests fail with `code` (tests)."""
+        return int(self._lib.rpca_server_inject_failure(self._h, int(stage), int(code)))
 
     def submit_raw(self, problem, tag: int, keep=None) -> int:
-        """Queue an rpca_problem whose device buffers the caller owns."""
+        """Queue an rpca_problem whose device buffers the caller owns.  The
+        library rejects a tag that names a request not yet reported."""
         rc = self._lib.rpca_server_submit(self._h, ctypes.byref(problem), int(tag))
         if rc == 0:
             self._live[int(tag)] = keep
         return int(rc)
 
     def submit(self, M, tag: int, lam: Optional[float] = None, mu: Optional[float] = None,
-               tol: float = 1e-6, maxit: int = 1000) -> None:
+               tol: float = 1e-6, maxit: int = 1000, timeout: Optional[float] = None) -> None:
         """Queue a solve of the device tensor M; L and S are allocated here and
-        returned with the completion."""
+        returned with the completion.  M must be a device tensor of the
+        server's dtype; `tag` must not name a request not yet reported.
+        `timeout` (seconds) overrides the server's timeout for this request."""
         import torch
-        from . import _problem
+        from . import _problem, _check_device, _dtype_code
+        if int(tag) in self._live:
+            raise ValueError(f"tag {tag} names a request that has not been reported")
+        if _dtype_code(M) != self._dtype:
+            raise ValueError("M's dtype differs from the server's dtype")
+        _check_device(M)
         L = torch.empty_like(M)
         S = torch.empty_like(M)
         p = _problem(M, L, S, lam, mu, tol, maxit)
-        rc = self.submit_raw(p, tag, keep=(M, L, S))
+        if timeout is not None:
+            self.set_timeout(timeout)
+        try:
+            rc = self.submit_raw(p, tag, keep=(M, L, S))
+        finally:
+            if timeout is not None:
+                self.set_timeout(self._timeout)
         if rc != 0:
             raise ValueError(f"request rejected: {rc}")
 

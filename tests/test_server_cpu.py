@@ -1,6 +1,8 @@
 """Admission and retirement logic of the serving loop, run without a device
 (RPCA_SERVER_SIMULATE: no HIP call is made; a request finishes after maxit
 iterations counted in quanta)."""
+import ctypes
+
 import pytest
 
 import paper_2506_10257_amd as rp
@@ -103,3 +105,81 @@ def test_create_rejects_bad_arguments(args):
     kw.update(args)
     with pytest.raises(ValueError):
         Server(**kw)
+
+
+def test_timeout_of_queued_and_active_requests():
+    """A request past its timeout completes with RPCA_ERR_TIMEOUT, queued or
+    active; the others are unaffected (simulated clock: 1 ms per step)."""
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=1, quantum=10, simulate=True)
+    srv.set_timeout(0.0035)                               # 3.5 steps
+    srv.submit_raw(_prob(4096, 20, 10000, 1 << 36), 0)  # "hangs": would need 1000 steps
+    srv.submit_raw(_prob(4096, 20, 20, 2 << 36), 1)     # queued behind it
+    srv.set_timeout(0.0)
+    srv.submit_raw(_prob(4096, 20, 20, 3 << 36), 2)     # no timeout
+    order, _ = _drain(srv)
+    got = {t: (st, it) for t, st, it in order}
+    assert got[0][0] == rp.RPCA_ERR_TIMEOUT and 0 < got[0][1] < 10000
+    assert got[1] == (rp.RPCA_ERR_TIMEOUT, 0)             # timed out while queued
+    assert got[2] == (rp.RPCA_NOT_CONVERGED, 20)
+    # the queued request expires first in the step where both pass 3.5 ms
+    assert [t for t, _, _ in order] == [1, 0, 2]
+    assert srv.pending() == (0, 0, 0, 0)
+    srv.close()
+
+
+def test_set_timeout_rejects_bad_values():
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 30, max_active=2, quantum=4, simulate=True)
+    for bad in (-1.0, float("nan")):
+        with pytest.raises(ValueError):
+            srv.set_timeout(bad)
+    srv.close()
+
+
+@pytest.mark.parametrize("code", [rp.RPCA_ERR_NOMEM, rp.RPCA_ERR_DEVICE])
+def test_failed_init_releases_requests(code):
+    """A failure while admitted requests are set up completes them with the
+    failure's code and gives their footprint back; later requests still run."""
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=4, quantum=8, simulate=True)
+    srv.submit_raw(_prob(4096, 20, 16, 1 << 36), 0)
+    srv.submit_raw(_prob(8192, 10, 16, 2 << 36), 1)
+    assert srv.inject_failure(code) == rp.RPCA_OK
+    got = srv.step()
+    assert sorted((c.tag, c.status) for c in got) == [(0, code), (1, code)]
+    assert srv.pending() == (0, 0, 0, 0)      # nothing queued, active or held
+    srv.submit_raw(_prob(4096, 20, 16, 3 << 36), 2)
+    order, _ = _drain(srv)
+    assert order == [(2, rp.RPCA_NOT_CONVERGED, 16)]
+    assert srv.inject_failure(5) == rp.RPCA_ERR_ARG          # codes are negative
+    assert srv._lib.rpca_server_inject_failure(srv._h, 9, -2) == rp.RPCA_ERR_ARG  # unknown stage
+    srv.close()
+
+
+def test_duplicate_tag_rejected_until_reported():
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=1, quantum=8, simulate=True)
+    assert srv.submit_raw(_prob(4096, 20, 8, 1 << 36), 7) == 0
+    assert srv.submit_raw(_prob(4096, 20, 8, 2 << 36), 7) == rp.RPCA_ERR_ARG   # queued
+    n = ctypes.c_int32(0)
+    buf = (_lib.RpcaCompletion * 4)()
+    assert srv._lib.rpca_server_step(srv._h, buf, 0, ctypes.byref(n)) == 0  # done, not reported
+    assert srv.submit_raw(_prob(4096, 20, 8, 2 << 36), 7) == rp.RPCA_ERR_ARG   # still held
+    got = srv.step()
+    assert [c.tag for c in got] == [7]
+    assert srv.submit_raw(_prob(4096, 20, 8, 2 << 36), 7) == 0                 # free again
+    srv.close()
+
+
+def test_python_submit_checks():
+    """Server.submit refuses a repeated tag, a dtype other than the server's
+    and a host tensor before anything reaches the library."""
+    import torch
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=2, quantum=8, simulate=True)
+    assert srv.submit_raw(_prob(4096, 20, 8, 1 << 36), 3, keep=()) == 0
+    M32 = torch.zeros(64, 4, dtype=torch.float32).t().contiguous().t()
+    with pytest.raises(ValueError, match="tag"):
+        srv.submit(M32, tag=3)
+    with pytest.raises(ValueError, match="dtype"):
+        srv.submit(M32.double(), tag=4)
+    with pytest.raises(ValueError, match="device"):
+        srv.submit(M32, tag=4)
+    assert srv.pending()[1] == 1
+    srv.close()
