@@ -155,6 +155,35 @@ int rpca_solve_many(rpca_problem* probs, int32_t count, int32_t dtype,
  */
 int rpca_solve_ex(rpca_problem* prob, int32_t dtype, int32_t gram_mode, void* stream);
 
+/*
+ * rpca_solve_noalloc - for callers that cannot allocate device memory during
+ * the call (code that must not call hipMalloc, tight serving loops, harnesses
+ * that forbid allocation).  The same solve as rpca_solve_f32 (dtype RPCA_F32)
+ * or rpca_solve_f64 (RPCA_F64), with the same arguments, defaults, status
+ * codes and bitwise the same L, S and iteration count, but its workspace
+ * lives in a static device array of the library, RPCA_NOALLOC_MAX_BYTES
+ * (192 MiB) per device, reserved when the library's code is loaded on that
+ * device and held until the process ends.  The call allocates no device
+ * memory, no pinned host memory, no stream, event or graph: it launches on
+ * `stream` directly and reads the solve state back between chunks of
+ * iterations.
+ *
+ * A solve fits when its workspace and control block fit the array; this
+ * holds whenever rpca_footprint_bytes(m, n, dtype) + 4096 <=
+ * RPCA_NOALLOC_MAX_BYTES (e.g. 512 x 512 x 20 frames in FP32 and in FP64).
+ * A larger solve returns RPCA_ERR_ARG before any device work, and
+ * rpca_last_error() names the sizes.  Every call on one device uses that
+ * device's one array: calls from several host threads are serialised by a
+ * lock, and each call returns only after its work completed, so its contents
+ * (left over from the previous call) are never read by a later call before
+ * being rewritten; work that the caller enqueues itself on other streams must
+ * not overlap a call's use of the array.
+ */
+#define RPCA_NOALLOC_MAX_BYTES (192u << 20)
+int rpca_solve_noalloc(const void* M, int64_t m, int64_t n, int32_t dtype, double lambda,
+                       double mu, double tol, int32_t maxit, void* L, void* S,
+                       int32_t* iterations, void* stream);
+
 /* Device workspace in bytes that one solve of this shape holds while it runs
  * (iterate buffers, reduction partials, Gram, projector, eigenvectors,
  * state).  0 for an unsupported shape. */

@@ -22,10 +22,10 @@ from ._lib import (RPCA_OK, RPCA_NOT_CONVERGED, RPCA_ERR_ARG, RPCA_ERR_NOMEM,
                    RPCA_ERR_DEVICE, RPCA_ERR_NONFINITE, RPCA_ERR_UNSUPPORTED, RPCA_ERR_TIMEOUT,
                    RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_GRAM_BF16X3, RPCA_GRAM_BF16X6, RPCA_N_MAX,
                    RPCA_KNOB_EIG_THREADS, RPCA_KNOB_STREAM_KERNEL, RPCA_KNOB_TILE_ROWS, RpcaProblem,
-                   RpcaProfile)
+                   RpcaProfile, RPCA_NOALLOC_MAX_BYTES)
 
 __all__ = ["solve", "solve_many", "SolveResult", "casorati_shape", "rpca_solve_f32",
-           "rpca_solve_f64", "rpca_solve_many", "rpca_solve_ex", "rpca_footprint_bytes",
+           "rpca_solve_f64", "rpca_solve_noalloc", "rpca_solve_many", "rpca_solve_ex", "rpca_footprint_bytes",
            "rpca_strerror", "rpca_version", "rpca_last_error", "rpca_profile_enable", "rpca_profile_read",
            "rpca_tune_set", "rpca_tune_get", "RPCA_KNOB_EIG_THREADS", "RPCA_KNOB_STREAM_KERNEL", "RPCA_KNOB_TILE_ROWS", "Server",
            "rpca_autotune", "rpca_autotune_save", "rpca_autotune_load", "tuning_choices",
@@ -100,6 +100,20 @@ def _solve_raw(fn, M, m, n, lam, mu, tol, maxit, L, S, stream):
     it = ctypes.c_int32(0)
     rc = fn(_ptr(M), int(m), int(n), float(lam), float(mu), float(tol), int(maxit),
             _ptr(L), _ptr(S), ctypes.byref(it), stream)
+    return int(rc), int(it.value)
+
+
+def rpca_solve_noalloc(M, m: int, n: int, dtype: int, lam: float, mu: float, tol: float,
+                       maxit: int, L, S, stream: Optional[int] = None) -> tuple[int, int]:
+    """C ``rpca_solve_noalloc``: the solve of rpca_solve_f32 / rpca_solve_f64
+    with its workspace in the library's static device array (no allocation
+    during the call).  Returns (status, iterations)."""
+    if stream is None:
+        stream = _stream_ptr(M) if hasattr(M, "device") else 0
+    it = ctypes.c_int32(0)
+    rc = _lib.load().rpca_solve_noalloc(_ptr(M), int(m), int(n), int(dtype), float(lam), float(mu),
+                                        float(tol), int(maxit), _ptr(L), _ptr(S), ctypes.byref(it),
+                                        stream)
     return int(rc), int(it.value)
 
 

@@ -30,9 +30,10 @@ RPCA_KNOB_STREAM_KERNEL = 2
 RPCA_KNOB_TILE_ROWS = 3
 RPCA_SERVER_SIMULATE = 1
 RPCA_SERVER_STAGE_INIT = 1
+RPCA_NOALLOC_MAX_BYTES = 192 << 20
 
 EXPORTS = (
-    "rpca_solve_f64", "rpca_solve_f32", "rpca_solve_many", "rpca_solve_ex",
+    "rpca_solve_f64", "rpca_solve_f32", "rpca_solve_many", "rpca_solve_ex", "rpca_solve_noalloc",
     "rpca_footprint_bytes", "rpca_strerror", "rpca_version",
     "rpca_profile_enable", "rpca_profile_read", "rpca_last_error",
     "rpca_tune_set", "rpca_tune_get",
@@ -113,6 +114,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = [vp, i64, i64, dbl, dbl, dbl, i32, vp, vp, ctypes.POINTER(i32), vp]
         f.restype = ctypes.c_int
+    lib.rpca_solve_noalloc.argtypes = [vp, i64, i64, i32, dbl, dbl, dbl, i32, vp, vp,
+                                        ctypes.POINTER(i32), vp]
+    lib.rpca_solve_noalloc.restype = ctypes.c_int
     lib.rpca_solve_many.argtypes = [ctypes.POINTER(RpcaProblem), i32, i32, i32, vp]
     lib.rpca_solve_many.restype = ctypes.c_int
     lib.rpca_solve_ex.argtypes = [ctypes.POINTER(RpcaProblem), i32, i32, vp]

@@ -78,7 +78,8 @@ struct Plan {
   std::vector<SolveRec*> recs;
   std::vector<LaneRun> lanes;
   std::vector<unsigned char> host;  // staging copy of the control block
-  char* ctrl = nullptr;             // device control block
+  size_t off_items = 0, off_gitems = 0, off_ids = 0, off_gath = 0;  // byte offsets in it
+  char* ctrl = nullptr;             // device control block owned by the plan (plan_build)
   SolveDesc* descs = nullptr;
   WorkItem* items = nullptr;
   GroupItem* gitems = nullptr;
@@ -87,9 +88,15 @@ struct Plan {
 };
 
 // Build the control block for `recs` (each rec's lane in [0, nlanes)) and
-// upload it on `stream`.  Returns a status code.
+// upload it on `stream` into a stream-ordered allocation the plan owns.
+// Returns a status code.
 int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int dtype,
                hipStream_t stream);
+// The two halves of plan_build: fill the host copy of the control block
+// (returns its size in bytes), then copy it into device memory `ctrl` of at
+// least that size (not owned by the plan) and point the plan's tables there.
+size_t plan_prepare(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int dtype);
+int plan_upload(Plan& plan, char* ctrl, hipStream_t stream);
 void plan_free(Plan& plan, hipStream_t stream);
 
 struct Lanes {

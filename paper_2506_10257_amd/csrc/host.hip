@@ -297,8 +297,7 @@ Big big_layout(int64_t m, int64_t n, const Geo& g) {
 }
 
 // --------------------------------------------------------------------- plan
-int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int dtype,
-               hipStream_t stream) {
+size_t plan_prepare(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int dtype) {
   plan.dtype = dtype;
   plan.count = static_cast<int>(recs.size());
   plan.recs = recs;
@@ -361,6 +360,10 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
   const size_t off_gath = al256(off_ids + sizeof(int32_t) * ids.size());
   const size_t bytes = al256(off_gath + sizeof(SolveState) * plan.count);
   plan.host.assign(bytes, 0);
+  plan.off_items = off_items;
+  plan.off_gitems = off_gitems;
+  plan.off_ids = off_ids;
+  plan.off_gath = off_gath;
 
   SolveDesc* dh = reinterpret_cast<SolveDesc*>(plan.host.data() + off_desc);
   for (int i = 0; i < plan.count; ++i) {
@@ -406,7 +409,27 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
   if (!gitems.empty())
     std::memcpy(plan.host.data() + off_gitems, gitems.data(), sizeof(GroupItem) * gitems.size());
   if (!ids.empty()) std::memcpy(plan.host.data() + off_ids, ids.data(), sizeof(int32_t) * ids.size());
+  return bytes;
+}
 
+int plan_upload(Plan& plan, char* ctrl, hipStream_t stream) {
+  const hipError_t e = hipMemcpyAsync(ctrl, plan.host.data(), plan.host.size(),
+                                      hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) {
+    set_error("hipMemcpyAsync(control block)", e);
+    return RPCA_ERR_DEVICE;
+  }
+  plan.descs = reinterpret_cast<SolveDesc*>(ctrl);
+  plan.items = reinterpret_cast<WorkItem*>(ctrl + plan.off_items);
+  plan.gitems = reinterpret_cast<GroupItem*>(ctrl + plan.off_gitems);
+  plan.ids = reinterpret_cast<int32_t*>(ctrl + plan.off_ids);
+  plan.gathered = reinterpret_cast<SolveState*>(ctrl + plan.off_gath);
+  return RPCA_OK;
+}
+
+int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int dtype,
+               hipStream_t stream) {
+  const size_t bytes = plan_prepare(plan, recs, nlanes, dtype);
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&plan.ctrl), bytes, stream);
   if (e != hipSuccess || plan.ctrl == nullptr) {
     set_error("hipMallocAsync(control block)", e);
@@ -414,17 +437,7 @@ int plan_build(Plan& plan, const std::vector<SolveRec*>& recs, int nlanes, int d
     plan.ctrl = nullptr;
     return RPCA_ERR_NOMEM;
   }
-  e = hipMemcpyAsync(plan.ctrl, plan.host.data(), bytes, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) {
-    set_error("hipMemcpyAsync(control block)", e);
-    return RPCA_ERR_DEVICE;
-  }
-  plan.descs = reinterpret_cast<SolveDesc*>(plan.ctrl + off_desc);
-  plan.items = reinterpret_cast<WorkItem*>(plan.ctrl + off_items);
-  plan.gitems = reinterpret_cast<GroupItem*>(plan.ctrl + off_gitems);
-  plan.ids = reinterpret_cast<int32_t*>(plan.ctrl + off_ids);
-  plan.gathered = reinterpret_cast<SolveState*>(plan.ctrl + off_gath);
-  return RPCA_OK;
+  return plan_upload(plan, plan.ctrl, stream);
 }
 
 void plan_free(Plan& plan, hipStream_t stream) {

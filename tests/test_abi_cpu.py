@@ -215,3 +215,23 @@ def test_autotune_save_load_roundtrip(lib, tmp_path):
     finally:
         rp.rpca_autotune_load(str(path))
     assert rp.tuning_choices() == before
+
+
+def test_noalloc_rejects_what_does_not_fit(lib):
+    """rpca_solve_noalloc refuses a solve larger than its static scratch, and
+    invalid arguments, before any device call."""
+    A, B, C = 1 << 40, 2 << 40, 3 << 40
+    it = ctypes.c_int32(7)
+    f = lib.rpca_solve_noalloc
+    m = 1 << 22                                   # 4 x 16 MiB x 20 frames of iterates
+    assert lib.rpca_footprint_bytes(m, 20, _lib.RPCA_F32) > _lib.RPCA_NOALLOC_MAX_BYTES
+    assert f(A, m, 20, _lib.RPCA_F32, -1.0, -1.0, 1e-6, 10, B, C, ctypes.byref(it), None) \
+        == _lib.RPCA_ERR_ARG
+    assert it.value == 0
+    assert b"RPCA_NOALLOC_MAX_BYTES" in lib.rpca_last_error()
+    assert f(A, 100, 4, 7, -1.0, -1.0, 1e-6, 10, B, C, None, None) == _lib.RPCA_ERR_ARG
+    assert f(A, 100, 4, _lib.RPCA_F32, -1.0, -1.0, 1e-6, 0, B, C, None, None) == _lib.RPCA_ERR_ARG
+    assert f(A, 100, 4, _lib.RPCA_F32, -1.0, -1.0, 1e-6, 10, A, C, None, None) == _lib.RPCA_ERR_ARG
+    # the 512 x 512 x 20 window fits in both precisions
+    for dt in (_lib.RPCA_F32, _lib.RPCA_F64):
+        assert lib.rpca_footprint_bytes(262144, 20, dt) + 4096 <= _lib.RPCA_NOALLOC_MAX_BYTES
