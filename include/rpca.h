@@ -78,14 +78,17 @@ extern "C" {
 #define RPCA_N_MAX 144   /* largest frame count n accepted by RPCA_F32 solves
                             (the FP64 eigensolve of the n x n Gram keeps the
                             packed G in the 160 KB of LDS; above 112 frames
-                            V stays in device memory); RPCA_F64 solves accept
-                            n <= 32                                         */
+                            V stays in device memory)                       */
+#define RPCA_N_MAX_F64 128  /* ... and by RPCA_F64 solves (one 64-row tile of
+                            doubles of every frame sits in LDS); 129 to 144
+                            frames in FP64 return RPCA_ERR_UNSUPPORTED      */
 
 /*
  * rpca_solve_f64 / rpca_solve_f32 - one RPCA solve.
  *
  *   M        device, m x n (layout above), not modified
  *   m, n     rows (pixels) and columns (frames); m >= 1, 1 <= n <= RPCA_N_MAX
+ *            (FP64: n <= RPCA_N_MAX_F64)
  *   lambda   sparsity weight of Eq. 2; <= 0 selects 1/sqrt(max(m, n))
  *   mu       fixed ALM penalty; <= 0 selects m*n / (4 sum|M_ij|) (Sec. II-A)
  *   tol      stopping threshold delta; <= 0 runs exactly maxit iterations
@@ -238,7 +241,9 @@ int rpca_profile_read(rpca_profile* out, int reset);
 /*   RPCA_KNOB_TILE_ROWS     pixel rows each workgroup of the tile kernel
  *                           walks (its tile shape along m) for one tile class
  *                           (`cls` = nb = 16, 32, ..., 144, the frame count
- *                           rounded up to 16; dtype RPCA_F32): a multiple of
+ *                           rounded up to 16; dtype RPCA_F32, and the setting
+ *                           also serves the FP64 solves of 33 to 128 frames,
+ *                           which always run the tile kernel): a multiple of
  *                           64 from 64 to 8192.  Fewer rows give more workgroups
  *                           (better occupancy for small launches), more rows
  *                           amortise the workgroup's Gram partial.  The

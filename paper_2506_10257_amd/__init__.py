@@ -20,7 +20,7 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import (RPCA_OK, RPCA_NOT_CONVERGED, RPCA_ERR_ARG, RPCA_ERR_NOMEM,
                    RPCA_ERR_DEVICE, RPCA_ERR_NONFINITE, RPCA_ERR_UNSUPPORTED, RPCA_ERR_TIMEOUT,
-                   RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_GRAM_BF16X3, RPCA_GRAM_BF16X6, RPCA_N_MAX,
+                   RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_GRAM_BF16X3, RPCA_GRAM_BF16X6, RPCA_N_MAX, RPCA_N_MAX_F64,
                    RPCA_KNOB_EIG_THREADS, RPCA_KNOB_STREAM_KERNEL, RPCA_KNOB_TILE_ROWS, RpcaProblem,
                    RpcaProfile, RPCA_NOALLOC_MAX_BYTES)
 
@@ -31,7 +31,7 @@ __all__ = ["solve", "solve_many", "SolveResult", "casorati_shape", "rpca_solve_f
            "rpca_autotune", "rpca_autotune_save", "rpca_autotune_load", "tuning_choices",
            "RPCA_OK", "RPCA_NOT_CONVERGED", "RPCA_ERR_ARG", "RPCA_ERR_NOMEM",
            "RPCA_ERR_DEVICE", "RPCA_ERR_NONFINITE", "RPCA_ERR_UNSUPPORTED", "RPCA_ERR_TIMEOUT", "RPCA_F32",
-           "RPCA_F64", "RPCA_GRAM_DEFAULT", "RPCA_GRAM_BF16X3", "RPCA_GRAM_BF16X6", "RPCA_N_MAX"]
+           "RPCA_F64", "RPCA_GRAM_DEFAULT", "RPCA_GRAM_BF16X3", "RPCA_GRAM_BF16X6", "RPCA_N_MAX", "RPCA_N_MAX_F64"]
 
 
 def _stream_ptr(t) -> int:

@@ -25,6 +25,7 @@ RPCA_GRAM_DEFAULT = 0
 RPCA_GRAM_BF16X3 = 1
 RPCA_GRAM_BF16X6 = 2
 RPCA_N_MAX = 144
+RPCA_N_MAX_F64 = 128
 RPCA_KNOB_EIG_THREADS = 1
 RPCA_KNOB_STREAM_KERNEL = 2
 RPCA_KNOB_TILE_ROWS = 3

@@ -25,10 +25,14 @@
 // step's eigenvectors V, on G~ = V^T G V, which is nearly diagonal once the
 // iteration settles.  The two products run on the f64 matrix cores
 // (W = G V goes through a per-solve global scratch buffer, since LDS holds G
-// and V already).  These classes serve FP32 solves only, so V is not
-// re-orthonormalised: the rounding of the rotations stays far below the
-// FP32 rounding of the data.  With V in global memory the projector
-// P = V diag(w) V^T is also formed on the f64 matrix cores.
+// and V already).  For FP64 solves V is first brought back to orthogonality
+// by one Newton-Schulz step V <- V (3I - V^T V) / 2 (also on the matrix
+// cores); for FP32 solves the rounding of the rotations stays far below the
+// FP32 rounding of the data and the step is skipped.  With V in global
+// memory the projector P = V diag(w) V^T is also formed on the f64 matrix
+// cores.
+#include <type_traits>
+
 #include "common.h"
 #include "eig_common.h"
 #include "launch.h"
@@ -155,6 +159,61 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     const gptr<double> Wg = as_global<double>(static_cast<void*>(d.escratch));
     // with V in global memory the products stop at nb (V is nb x nb)
     const int nt16 = VG ? nb / 16 : NT16;
+    if constexpr (std::is_same<T, double>::value) {
+      // FP64 solves: one Newton-Schulz step V <- V (3I - V^T V) / 2 first, so
+      // the rounding of the rotations does not accumulate over the solve.
+      // C = V^T V goes to the scratch; each wave keeps its blocks of V C in
+      // registers until every wave has read V, then writes its entries of
+      // the new V (each entry has one owner).
+      auto vat = [&](int i, int j) -> double {
+        return VG ? static_cast<double>(Vg[i * nb + j]) : Vs[i * LDV + j];
+      };
+      for (int t = wv; t < nt16 * nt16; t += NWV) {
+        const int bi = t / nt16, bj = t - (t / nt16) * nt16;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int kk = 0; kk < nt16 * 4; ++kk) {
+          const int kq = 4 * kk + (l >> 4);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(vat(kq, 16 * bi + (l & 15)),
+                                                     vat(kq, 16 * bj + (l & 15)), acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wg[(16 * bi + (l >> 4) + 4 * r) * NMAX + 16 * bj + (l & 15)] = acc[r];
+      }
+      __syncthreads();
+      constexpr int MV = (NT16 * NT16 + NWV - 1) / NWV;
+      d4 vc[MV];
+#pragma unroll
+      for (int q = 0; q < MV; ++q) {
+        const int t = wv + q * NWV;
+        vc[q] = d4{0.0, 0.0, 0.0, 0.0};
+        if (t < nt16 * nt16) {
+          const int bi = t / nt16, bj = t - (t / nt16) * nt16;
+#pragma unroll 4
+          for (int kk = 0; kk < nt16 * 4; ++kk) {
+            const int kq = 4 * kk + (l >> 4);
+            vc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(vat(16 * bi + (l & 15), kq),
+                                                         Wg[kq * NMAX + 16 * bj + (l & 15)], vc[q], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MV; ++q) {
+        const int t = wv + q * NWV;
+        if (t < nt16 * nt16) {
+          const int bi = t / nt16, bj = t - (t / nt16) * nt16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * bi + (l >> 4) + 4 * r, j = 16 * bj + (l & 15);
+            const double v1 = fma(-0.5, vc[q][r], 1.5 * vat(i, j));
+            if constexpr (VG) Vg[i * nb + j] = v1;
+            else Vs[i * LDV + j] = v1;
+          }
+        }
+      }
+      __syncthreads();
+    }
     for (int t = wv; t < nt16 * nt16; t += NWV) {
       const int bi = t / nt16, bj = t - (t / nt16) * nt16;
       d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -427,15 +486,20 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
 hipError_t launch_eig_wide(int dtype, int ncls, int grid, hipStream_t stream, const SolveDesc* descs,
                            const int32_t* ids) {
   if (grid <= 0) return hipSuccess;
-  // these classes run FP32 solves only (FP64 register classes stop at 32)
-  if (dtype != 1) return hipErrorInvalidValue;
   const dim3 g(grid), b(kEigWideThreads);
-  if (ncls == kEigWideMaxN)
-    RPCA_LAUNCH((k_eig_wide<float, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
-  else if (ncls == kEigHugeMaxN)
-    RPCA_LAUNCH((k_eig_wide<float, kEigHugeMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
-  else
+  if (ncls == kEigWideMaxN) {
+    if (dtype == 1)
+      RPCA_LAUNCH((k_eig_wide<float, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+    else
+      RPCA_LAUNCH((k_eig_wide<double, kEigWideMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+  } else if (ncls == kEigHugeMaxN) {
+    if (dtype == 1)
+      RPCA_LAUNCH((k_eig_wide<float, kEigHugeMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+    else
+      RPCA_LAUNCH((k_eig_wide<double, kEigHugeMaxN, kEigWideThreads>), g, b, 0, stream, descs, ids);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

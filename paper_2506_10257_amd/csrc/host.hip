@@ -129,7 +129,9 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 hipError_t launch_stream(int dtype, int key, int mode, int grid, hipStream_t s, const SolveDesc* d,
                          const WorkItem* it) {
   const int nb = key & 0xff, kind = (key >> 8) & 1, prec = (key >> 9) & 3;
-  if (kind == 1) return launch_wide(nb, mode, prec, grid, s, d, it);
+  if (kind == 1)
+    return dtype == RPCA_F32 ? launch_wide_f32(nb, mode, prec, grid, s, d, it)
+                             : launch_wide_f64(nb, mode, grid, s, d, it);
   return dtype == RPCA_F32 ? launch_stream_f32(nb, mode, grid, s, d, it)
                            : launch_stream_f64(nb, mode, grid, s, d, it);
 }
@@ -252,7 +254,7 @@ bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g) {
     g.tiles = static_cast<int>(tiles);
     g.tps = 1;  // one tile per work item (and per partial slot)
   } else {
-    if (dtype != RPCA_F32 || n > kEigHugeMaxN) return false;
+    if (n > (dtype == RPCA_F32 ? kEigHugeMaxN : kF64MaxN)) return false;
     g.nb = static_cast<int>((n + 15) / 16 * 16);
     const int64_t tiles = (m + kWideRows - 1) / kWideRows;
     g.tiles = static_cast<int>(tiles);

@@ -52,14 +52,17 @@ hipError_t launch_reset_states(int count, hipStream_t stream, const SolveDesc* d
 // Returns 16, 32, 64, kEigWideMaxN or kEigHugeMaxN (0 if n is too large).
 int eig_class(int n);
 // Classes above 64 frames: the in-place eigensolver, ncls = kEigWideMaxN
-// (V in LDS) or kEigHugeMaxN (V in global memory); FP32 solves only.
+// (V in LDS) or kEigHugeMaxN (V in global memory).
 hipError_t launch_eig_wide(int dtype, int ncls, int grid, hipStream_t stream,
                            const SolveDesc* descs, const int32_t* ids);
-// MFMA streaming kernel (FP32 storage): nb a multiple of 16 up to 144;
+// MFMA streaming kernel.  FP32 storage: nb a multiple of 16 up to 144;
 // prec 0 = FP32 rebuild / FP64 Gram, 1 = split-BF16 (3 products) for both,
-// 2 = split-BF16 (6 products).
-hipError_t launch_wide(int nb, int mode, int prec, int grid, hipStream_t stream,
-                       const SolveDesc* descs, const WorkItem* items);
+// 2 = split-BF16 (6 products).  FP64 storage: nb = 48, 64, ..., 128, both
+// contractions in FP64.
+hipError_t launch_wide_f32(int nb, int mode, int prec, int grid, hipStream_t stream,
+                           const SolveDesc* descs, const WorkItem* items);
+hipError_t launch_wide_f64(int nb, int mode, int grid, hipStream_t stream, const SolveDesc* descs,
+                           const WorkItem* items);
 bool eig_threads_valid(int ncls, int nt);
 int eig_threads(int dtype, int ncls);
 bool set_eig_threads(int dtype, int ncls, int nt);

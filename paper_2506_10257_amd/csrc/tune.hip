@@ -126,7 +126,6 @@ int rpca_autotune(int32_t dtype, int64_t rows, void* stream) {
 
   // 1. eigensolver workgroup size per class
   for (int cls : {16, 32, 64}) {
-    if (dtype == RPCA_F64 && cls > 32) break;
     Bufs b;
     rc = alloc_window(b, kTuneEigRows, cls, dtype, s);
     if (rc != RPCA_OK) {

@@ -114,11 +114,15 @@ def test_frame_limits(lib):
     A, B, C = 1 << 40, 2 << 40, 3 << 40
     assert _lib.RPCA_N_MAX == 144
     assert _call(lib, A, 100, 145, B, C)[0] == _lib.RPCA_ERR_ARG
-    assert _call(lib, A, 100, 33, B, C, fn="rpca_solve_f64")[0] == _lib.RPCA_ERR_UNSUPPORTED
+    # FP64 solves stop at 128 frames (RPCA_N_MAX_F64), FP32 solves at 144
+    assert _lib.RPCA_N_MAX_F64 == 128
+    assert _call(lib, A, 100, 129, B, C, fn="rpca_solve_f64")[0] == _lib.RPCA_ERR_UNSUPPORTED
     for n in (112, 113, 128, 132, 144):
         assert lib.rpca_footprint_bytes(4096, n, _lib.RPCA_F32) > 0
+    for n in (33, 64, 65, 100, 112, 113, 128):
+        assert lib.rpca_footprint_bytes(4096, n, _lib.RPCA_F64) > 0
     assert lib.rpca_footprint_bytes(4096, 145, _lib.RPCA_F32) == 0
-    assert lib.rpca_footprint_bytes(4096, 33, _lib.RPCA_F64) == 0
+    assert lib.rpca_footprint_bytes(4096, 129, _lib.RPCA_F64) == 0
     # the 144-frame class holds a 144 x 144 FP64 scratch for the eigensolver's
     # warm start beside its V, P and partials
     assert (lib.rpca_footprint_bytes(4096, 132, _lib.RPCA_F32)

@@ -17,8 +17,6 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_eig_threads_bitwise(n, cls, dtype):
     device()
-    if dtype == np.float64 and n > 32:
-        pytest.skip("FP64 streaming classes stop at 32 frames")
     X = batch_window(64, 64, n, 3100 + n).X()
     M = to_dev(X, dtype)
     dt = rp.RPCA_F64 if dtype == np.float64 else rp.RPCA_F32

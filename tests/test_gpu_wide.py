@@ -171,3 +171,64 @@ def test_bf16x6_meets_fp32_bar(H, W, n):
     ref = rpca(X, tol=1e-6, maxit=1000)
     L, S, it, rc = _solve(X, gram_mode=rp.RPCA_GRAM_BF16X6, tol=1e-6, maxit=1000)
     _check(f"bf16x6 {H}x{W}x{n}", w, ref, L, S, it)
+
+
+# FP64 solves of 33 to 128 frames: the FP64 tile kernel (both contractions on
+# the f64 matrix cores) and, above 64 frames, the in-place eigensolver with a
+# Newton-Schulz re-orthonormalisation of its warm start.  Held to the FP64
+# bar: 1e-10 in L and S with the same iteration count and status.
+FP64_WIDE = [(48, 50, 40), (40, 41, 60), (36, 30, 64), (40, 44, 65), (44, 50, 100),
+             (40, 37, 112), (36, 40, 113), (32, 41, 128)]
+
+
+def _solve64(X, tol=1e-7, maxit=300):
+    M = to_dev(X, np.float64)
+    r = rp.solve(M, tol=tol, maxit=maxit)
+    return to_host(r.L), to_host(r.S), r.iterations, r.status
+
+
+@pytest.mark.parametrize("H,W,n", FP64_WIDE)
+def test_wide_fp64_matches_oracle(H, W, n):
+    device()
+    w = batch_window(H, W, n, 7700 + n)
+    X = w.X()
+    ref = rpca(X, tol=1e-7, maxit=300)
+    L, S, it, rc = _solve64(X)
+    _check(f"wide fp64 {H}x{W}x{n}", w, ref, L, S, it, bar=1e-10, it_slack=0)
+    assert rc == ref.status
+
+
+@pytest.mark.parametrize("n", [60, 100, 128])
+@pytest.mark.parametrize("k", [1, 2, 7])
+def test_wide_fp64_iterate_parity(n, k):
+    """k-th iterate (tol = 0); k >= 2 runs the warm start with the
+    Newton-Schulz step."""
+    device()
+    X = batch_window(40, 44, n, 7800 + n).X()
+    ref = rpca(X, tol=0.0, maxit=k)
+    L, S, it, rc = _solve64(X, tol=0.0, maxit=k)
+    eL, eS = rel_fro(L, ref.L), rel_fro(S, ref.S)
+    report(f"wide fp64 iterate n={n} k={k}", relL=eL, relS=eS)
+    assert it == k and eL <= 1e-10 and eS <= 1e-10
+
+
+def test_wide_fp64_batch_bitwise_equals_alone():
+    import torch
+    device()
+    shapes = [(40, 40, 100), (32, 48, 20), (48, 40, 40), (30, 30, 128), (64, 64, 10), (36, 36, 70)]
+    Ms = [to_dev(batch_window(H, W, n, 7900 + i).X(), np.float64) for i, (H, W, n) in enumerate(shapes)]
+    alone = [rp.solve(M, tol=1e-7, maxit=200) for M in Ms]
+    many = rp.solve_many(Ms, tol=1e-7, maxit=200)
+    torch.cuda.synchronize()
+    for a, b in zip(alone, many):
+        assert a.iterations == b.iterations
+        assert torch.equal(a.L, b.L) and torch.equal(a.S, b.S)
+
+
+def test_fp64_above_128_frames_unsupported():
+    import torch
+    device()
+    M = torch.ones((129, 64), dtype=torch.float64, device="cuda:0").t()
+    L, S = torch.empty_like(M), torch.empty_like(M)
+    rc, it = rp.rpca_solve_f64(M, 64, 129, -1.0, -1.0, 1e-7, 10, L, S)
+    assert rc == rp.RPCA_ERR_UNSUPPORTED and it == 0
