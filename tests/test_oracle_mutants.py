@@ -12,7 +12,7 @@ from tests import test_oracle_pins as P
 
 _orig = {name: getattr(O, name) for name in
          ("shrink", "svt", "l_step", "s_step", "dual_step", "converged",
-          "default_mu", "default_lambda")}
+          "default_mu", "default_lambda", "rpca")}
 
 
 def _svt_no_clamp(M, tau):
@@ -28,6 +28,28 @@ def _svt_transposed(M, tau):
     U, s, Vt = np.linalg.svd(M, full_matrices=False)
     w = np.maximum(s - tau, 0.0)
     return ((U * w) @ Vt).T.reshape(M.shape)
+
+
+def _dual_stale():
+    """Eq. 6 with the L and S of the previous iteration (zero before the
+    first), instead of the ones just computed."""
+    prev = {}
+
+    def dual(Y, X, L, S, mu):
+        Lp, Sp = prev.get("L"), prev.get("S")
+        if Lp is None or Lp.shape != L.shape:
+            Lp, Sp = np.zeros_like(L), np.zeros_like(S)
+        prev["L"], prev["S"] = L, S
+        return Y + mu * (X - Lp - Sp)
+    return dual
+
+
+def _iters_off_by_one(*args, **kw):
+    """The iteration count reported one too high (counting from zero)."""
+    r = _orig["rpca"](*args, **kw)
+    if r.iterations > 0:
+        r.iterations += 1
+    return r
 
 
 MUTANTS = {
@@ -50,16 +72,19 @@ MUTANTS = {
     "dual_minus": lambda Y, X, L, S, mu: Y - mu * (X - L - S),
     "dual_drop_S": lambda Y, X, L, S, mu: Y + mu * (X - L),
     "dual_over_mu": lambda Y, X, L, S, mu: Y + (X - L - S) / mu,
+    "dual_stale_L_S": _dual_stale(),
     # stopping rule and defaults
     "stop_not_strict": lambda rel, tol: rel <= tol,
     "mu_frame_dims": lambda X: float(X.shape[0]) / (4.0 * float(np.sum(np.abs(X)))),
     "mu_fro_norm": lambda X: float(X.size) / (4.0 * float(np.linalg.norm(X))),
     "lambda_min_dim": lambda m, n: 1.0 / np.sqrt(float(min(m, n))),
+    "iters_off_by_one": _iters_off_by_one,
 }
 
 TARGET = {
     "L_step": "l_step", "S_step": "s_step", "svt": "svt", "shrink": "shrink",
     "dual": "dual_step", "stop": "converged", "mu": "default_mu", "lambda": "default_lambda",
+    "iters": "rpca",
 }
 
 

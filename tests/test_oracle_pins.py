@@ -257,7 +257,8 @@ def test_zero_and_nonfinite_inputs():
 
 
 # ------------------------------------------------------- whole-loop pins
-@pytest.mark.parametrize("m,n,rank,rho,seed", [(2000, 40, 1, 0.05, 7), (300, 300, 10, 0.05, 8)])
+@pytest.mark.parametrize("m,n,rank,rho,seed", [(2000, 40, 1, 0.05, 7), (300, 300, 10, 0.05, 8),
+                                               (500, 500, 25, 0.05, 9)])
 def test_planted_recovery(m, n, rank, rho, seed):
     """PCP recovers a planted low-rank + sparse pair (Eq. 2); the iteration must
     get there to the stopping accuracy."""
