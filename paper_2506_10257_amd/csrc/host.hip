@@ -681,6 +681,45 @@ namespace {
     }                                             \
   } while (0)
 
+// Streams, events and pinned state buffers of the calls made by one host
+// thread on one device: created on the first call, reused by later calls
+// (their creation costs more than a small solve), never destroyed (process
+// exit releases them).
+struct LaneCache {
+  Lanes L;
+  bool ok = false;
+};
+thread_local LaneCache* t_lane_cache[64] = {};
+
+// A view of the first `nlanes` lanes of this thread's cached set for `dev`
+// with room for `count` solve states, or an error code.
+int cached_lanes(int dev, int nlanes, int count, Lanes& view) {
+  if (dev < 0 || dev >= 64) return RPCA_ERR_DEVICE;
+  LaneCache*& c = t_lane_cache[dev];
+  if (c == nullptr) c = new LaneCache();
+  if (!c->ok) {
+    lanes_destroy(c->L);
+    const int rc = lanes_create(c->L, kMaxLanes);
+    if (rc != RPCA_OK) {
+      lanes_destroy(c->L);
+      return rc;
+    }
+    c->ok = true;
+  }
+  const int rc = lanes_reserve_pinned(c->L, count);
+  if (rc != RPCA_OK) return rc;
+  view = Lanes{};
+  view.s.assign(c->L.s.begin(), c->L.s.begin() + nlanes);
+  view.join.assign(c->L.join.begin(), c->L.join.begin() + nlanes);
+  view.fork = c->L.fork;
+  for (int k = 0; k < 2; ++k) {
+    view.pinned[k] = c->L.pinned[k];
+    view.snap[k] = c->L.snap[k];
+  }
+  view.pinned_count = c->L.pinned_count;
+  return RPCA_OK;
+}
+
 int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStream_t user) {
   g_last_error[0] = '\0';
   if (count < 1 || probs == nullptr) return RPCA_ERR_ARG;
@@ -728,16 +767,8 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   }
   assign_lanes(ptrs, nlanes);
 
-  rc = lanes_create(L, nlanes);
-  if (rc != RPCA_OK) {
-    lanes_destroy(L);
-    return rc;
-  }
-  rc = lanes_reserve_pinned(L, count);
-  if (rc != RPCA_OK) {
-    lanes_destroy(L);
-    return rc;
-  }
+  rc = cached_lanes(dev, nlanes, count, L);
+  if (rc != RPCA_OK) return rc;
   hipStream_t s0 = L.s[0];
   if (prof) t_evs = &evs;
 
@@ -769,6 +800,10 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   if (rc != RPCA_OK) goto done;
   CK(enqueue_reset_states(plan, s0));
   CK(enqueue_init(plan, L));
+  // The init passes of lanes 1.. run on their own streams; the iteration
+  // chunks (a graph launched on lane 0, or direct launches forked from it)
+  // must come after them, so join them into lane 0 first.
+  CK(join_lanes(L));
 
   {
     int launched = 0;  // iterations enqueued (eigensolve launches per solve)
@@ -909,7 +944,7 @@ done:
     if (arena) (void)hipFreeAsync(arena, L.s[0]);
     (void)hipStreamSynchronize(L.s[0]);
   }
-  lanes_destroy(L);
+  // L is a view of the thread's cached lanes: nothing to destroy
   return rc;
 }
 
