@@ -47,7 +47,9 @@ def tuning_summary() -> dict:
     return {"eig_threads_f32": {str(c): v for (dt, c), v in ch["eig_threads"].items() if dt == rp.RPCA_F32},
             "eig_threads_f64": {str(c): v for (dt, c), v in ch["eig_threads"].items() if dt == rp.RPCA_F64},
             "tile_kernel_classes": [c for c, v in ch["stream_kernel"].items() if v == 1],
-            "tile_rows": {str(nb): v for nb, v in ch["tile_rows"].items()}}
+            "tile_rows": {str(nb): v for nb, v in ch["tile_rows"].items()},
+            "reg_tiles_f32": {str(c): v for (dt, c), v in ch["reg_tiles"].items() if dt == rp.RPCA_F32},
+            "reg_tiles_f64": {str(c): v for (dt, c), v in ch["reg_tiles"].items() if dt == rp.RPCA_F64}}
 
 
 def kernel_source_sha() -> str:

@@ -256,6 +256,20 @@ int rpca_profile_read(rpca_profile* out, int reset);
  *                           a given setting they are the same alone or in a
  *                           batch.                                          */
 #define RPCA_KNOB_TILE_ROWS 3
+/*   RPCA_KNOB_REG_TILES     256-row tiles each workgroup of the register
+ *                           kernel walks, for one register class (`cls` as for
+ *                           RPCA_KNOB_STREAM_KERNEL, or 4 ... 32 with
+ *                           RPCA_F64): 1 to 16; default 2 for the RPCA_F64
+ *                           classes of up to 20 frames, else 1.  A workgroup walks its tiles in
+ *                           order and writes one partial for all of them
+ *                           (fewer partials to reduce), at the cost of about
+ *                           40 registers for the Gram accumulators that the
+ *                           loop keeps live.  A solve of T tiles uses at most
+ *                           max(1, T / 256) tiles per workgroup.  Results
+ *                           differ between settings by rounding (the partial
+ *                           sums regroup); for a given setting they are the
+ *                           same alone or in a batch.                       */
+#define RPCA_KNOB_REG_TILES 4
 int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value);
 int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls);
 

@@ -21,13 +21,13 @@ from . import _lib
 from ._lib import (RPCA_OK, RPCA_NOT_CONVERGED, RPCA_ERR_ARG, RPCA_ERR_NOMEM,
                    RPCA_ERR_DEVICE, RPCA_ERR_NONFINITE, RPCA_ERR_UNSUPPORTED, RPCA_ERR_TIMEOUT,
                    RPCA_F32, RPCA_F64, RPCA_GRAM_DEFAULT, RPCA_GRAM_BF16X3, RPCA_GRAM_BF16X6, RPCA_N_MAX, RPCA_N_MAX_F64,
-                   RPCA_KNOB_EIG_THREADS, RPCA_KNOB_STREAM_KERNEL, RPCA_KNOB_TILE_ROWS, RpcaProblem,
+                   RPCA_KNOB_EIG_THREADS, RPCA_KNOB_STREAM_KERNEL, RPCA_KNOB_TILE_ROWS, RPCA_KNOB_REG_TILES, RpcaProblem,
                    RpcaProfile, RPCA_NOALLOC_MAX_BYTES)
 
 __all__ = ["solve", "solve_many", "SolveResult", "casorati_shape", "rpca_solve_f32",
            "rpca_solve_f64", "rpca_solve_noalloc", "rpca_solve_many", "rpca_solve_ex", "rpca_footprint_bytes",
            "rpca_strerror", "rpca_version", "rpca_last_error", "rpca_profile_enable", "rpca_profile_read",
-           "rpca_tune_set", "rpca_tune_get", "RPCA_KNOB_EIG_THREADS", "RPCA_KNOB_STREAM_KERNEL", "RPCA_KNOB_TILE_ROWS", "Server",
+           "rpca_tune_set", "rpca_tune_get", "RPCA_KNOB_EIG_THREADS", "RPCA_KNOB_STREAM_KERNEL", "RPCA_KNOB_TILE_ROWS", "RPCA_KNOB_REG_TILES", "Server",
            "rpca_autotune", "rpca_autotune_save", "rpca_autotune_load", "tuning_choices",
            "RPCA_OK", "RPCA_NOT_CONVERGED", "RPCA_ERR_ARG", "RPCA_ERR_NOMEM",
            "RPCA_ERR_DEVICE", "RPCA_ERR_NONFINITE", "RPCA_ERR_UNSUPPORTED", "RPCA_ERR_TIMEOUT", "RPCA_F32",
@@ -182,7 +182,7 @@ def rpca_autotune_load(path: str) -> int:
 
 def tuning_choices() -> dict:
     """Current knob values: {"eig_threads": {(dtype, cls): v}, "stream_kernel": {cls: v},
-    "tile_rows": {nb: rows}}."""
+    "tile_rows": {nb: rows}, "reg_tiles": {(dtype, cls): tiles}}."""
     out = {"eig_threads": {}, "stream_kernel": {}, "tile_rows": {}}
     for dt in (RPCA_F64, RPCA_F32):
         for cls in (16, 32, 64):
@@ -191,6 +191,11 @@ def tuning_choices() -> dict:
         out["stream_kernel"][cls] = rpca_tune_get(RPCA_KNOB_STREAM_KERNEL, RPCA_F32, cls)
     for nb in range(16, 145, 16):
         out["tile_rows"][nb] = rpca_tune_get(RPCA_KNOB_TILE_ROWS, RPCA_F32, nb)
+    out["reg_tiles"] = {}
+    for cls in (4, 8, 10, 12, 16, 20, 24, 28, 32, 40, 48, 56, 60, 64):
+        out["reg_tiles"][(RPCA_F32, cls)] = rpca_tune_get(RPCA_KNOB_REG_TILES, RPCA_F32, cls)
+    for cls in (4, 8, 10, 12, 16, 20, 24, 28, 32):
+        out["reg_tiles"][(RPCA_F64, cls)] = rpca_tune_get(RPCA_KNOB_REG_TILES, RPCA_F64, cls)
     return out
 
 

@@ -29,6 +29,7 @@ RPCA_N_MAX_F64 = 128
 RPCA_KNOB_EIG_THREADS = 1
 RPCA_KNOB_STREAM_KERNEL = 2
 RPCA_KNOB_TILE_ROWS = 3
+RPCA_KNOB_REG_TILES = 4
 RPCA_SERVER_SIMULATE = 1
 RPCA_SERVER_STAGE_INIT = 1
 RPCA_NOALLOC_MAX_BYTES = 192 << 20

@@ -28,11 +28,13 @@ struct Geo {
   int nb = 0, tiles = 0, tps = 1, slots = 0, groups = 0, pstride = 0;
   int kind = 0;  // streaming kernel: 0 register (thread per row), 1 MFMA tiles
   int prec = 0;  // contraction precision: 0 storage/FP64, 1 BF16x3, 2 BF16x6
+  int mt = 0;    // register kernel whose work items walk several tiles
   size_t es = 0;
 };
 
-// Launch-class key of a solve: frame class, kernel kind, precision.
-inline int class_key(const Geo& g) { return g.nb | (g.kind << 8) | (g.prec << 9); }
+// Launch-class key of a solve: frame class, kernel kind, precision, and for
+// the register kernel whether it is the multi-tile variant.
+inline int class_key(const Geo& g) { return g.nb | (g.kind << 8) | (g.prec << 9) | (g.mt << 11); }
 
 // Byte offsets of one solve's device memory.
 struct Big {
@@ -144,6 +146,9 @@ int nb_class(int64_t n, int dtype);
 // FP32 register classes: streaming kernel choice (0 register, 1 MFMA tiles).
 int stream_kernel_choice(int cls);
 bool set_stream_kernel_choice(int cls, int v);
+// tiles per workgroup of the register kernel (-1: no such class)
+int reg_tiles(int dtype, int cls);
+bool set_reg_tiles(int dtype, int cls, int v);
 // rows per workgroup of the tile kernel for tile class nb (-1: no such class)
 int tile_rows(int nb);
 bool set_tile_rows(int nb, int rows);

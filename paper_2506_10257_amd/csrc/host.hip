@@ -129,11 +129,12 @@ bool overlap(const void* a, const void* b, size_t bytes) {
 hipError_t launch_stream(int dtype, int key, int mode, int grid, hipStream_t s, const SolveDesc* d,
                          const WorkItem* it) {
   const int nb = key & 0xff, kind = (key >> 8) & 1, prec = (key >> 9) & 3;
+  const bool mt = ((key >> 11) & 1) != 0;
   if (kind == 1)
     return dtype == RPCA_F32 ? launch_wide_f32(nb, mode, prec, grid, s, d, it)
                              : launch_wide_f64(nb, mode, grid, s, d, it);
-  return dtype == RPCA_F32 ? launch_stream_f32(nb, mode, grid, s, d, it)
-                           : launch_stream_f64(nb, mode, grid, s, d, it);
+  return dtype == RPCA_F32 ? launch_stream_f32(nb, mode, mt, grid, s, d, it)
+                           : launch_stream_f64(nb, mode, mt, grid, s, d, it);
 }
 
 #ifdef RPCA_TRACE
@@ -239,6 +240,35 @@ bool set_stream_kernel_choice(int cls, int v) {
   return true;
 }
 
+// Tiles each workgroup of the register kernel walks, per dtype and register
+// class (index: class value 0..64).
+std::atomic<int> g_reg_tiles[2][kEigMaxN + 1];
+std::once_flag g_reg_tiles_once;
+void init_reg_tiles() {
+  std::call_once(g_reg_tiles_once, [] {
+    // defaults from timing on MI355X (512 x 512 x 20 window): two tiles per
+    // workgroup for FP64 up to 20 frames (update pass 39.5 against 41.9 us),
+    // one for FP32,
+    // whose single-tile kernel keeps a higher occupancy (27.5 against 28.4)
+    for (int c = 0; c <= kEigMaxN; ++c) {
+      g_reg_tiles[0][c].store(c <= 20 ? 2 : 1);  // the loop leaves 24-32 at one wave per SIMD
+      g_reg_tiles[1][c].store(1);
+    }
+  });
+}
+
+int reg_tiles(int dtype, int cls) {
+  if (cls < 0 || cls > kEigMaxN || nb_class(cls, dtype) != cls) return -1;
+  init_reg_tiles();
+  return g_reg_tiles[dtype == RPCA_F32 ? 1 : 0][cls].load(std::memory_order_relaxed);
+}
+
+bool set_reg_tiles(int dtype, int cls, int v) {
+  if (reg_tiles(dtype, cls) < 0 || v < 1 || v > 16) return false;
+  g_reg_tiles[dtype == RPCA_F32 ? 1 : 0][cls].store(v, std::memory_order_relaxed);
+  return true;
+}
+
 bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g) {
   if (m < 1 || n < 1 || n > RPCA_N_MAX) return false;
   if (m >= (int64_t(1) << 30)) return false;  // row offsets are 32-bit byte offsets
@@ -252,7 +282,13 @@ bool geometry(int64_t m, int64_t n, int dtype, int gram_mode, Geo& g) {
     g.nb = reg;
     const int64_t tiles = (m + kTile - 1) / kTile;
     g.tiles = static_cast<int>(tiles);
-    g.tps = 1;  // one tile per work item (and per partial slot)
+    // tiles per work item (and per partial slot): the class's knob, capped
+    // so that the solve still spreads over at least 256 workgroups where it
+    // has 256 tiles to give
+    const int64_t cap = std::max<int64_t>(1, tiles / 256);
+    const int want = reg_tiles(dtype, reg);
+    g.tps = static_cast<int>(std::min<int64_t>(want, cap));
+    g.mt = want > 1 ? 1 : 0;
   } else {
     if (n > (dtype == RPCA_F32 ? kEigHugeMaxN : kF64MaxN)) return false;
     g.nb = static_cast<int>((n + 15) / 16 * 16);
@@ -1037,6 +1073,7 @@ int rpca_tune_set(int32_t knob, int32_t dtype, int32_t cls, int32_t value) {
     if (dtype != RPCA_F32) return RPCA_ERR_ARG;
     return set_tile_rows(cls, value) ? RPCA_OK : RPCA_ERR_ARG;
   }
+  if (knob == RPCA_KNOB_REG_TILES) return set_reg_tiles(dtype, cls, value) ? RPCA_OK : RPCA_ERR_ARG;
   return RPCA_ERR_ARG;
 }
 
@@ -1054,6 +1091,10 @@ int rpca_tune_get(int32_t knob, int32_t dtype, int32_t cls) {
   if (knob == RPCA_KNOB_TILE_ROWS) {
     if (dtype != RPCA_F32) return RPCA_ERR_ARG;
     const int v = tile_rows(cls);
+    return v > 0 ? v : RPCA_ERR_ARG;
+  }
+  if (knob == RPCA_KNOB_REG_TILES) {
+    const int v = reg_tiles(dtype, cls);
     return v > 0 ? v : RPCA_ERR_ARG;
   }
   return RPCA_ERR_ARG;

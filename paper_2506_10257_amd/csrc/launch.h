@@ -36,9 +36,10 @@ constexpr int kClassesF64[] = {4, 8, 10, 12, 16, 20, 24, 28, 32};
 enum StreamMode { kModeInit = 0, kModeUpdate = 1, kModeFinalize = 2, kModeWarm = 3 };
 
 // dtype 0 = FP64, 1 = FP32 (as RPCA_F64 / RPCA_F32).
-hipError_t launch_stream_f32(int nb, int mode, int grid, hipStream_t stream,
+// mt: the multi-tile register kernel (work items of more than one tile).
+hipError_t launch_stream_f32(int nb, int mode, bool mt, int grid, hipStream_t stream,
                              const SolveDesc* descs, const WorkItem* items);
-hipError_t launch_stream_f64(int nb, int mode, int grid, hipStream_t stream,
+hipError_t launch_stream_f64(int nb, int mode, bool mt, int grid, hipStream_t stream,
                              const SolveDesc* descs, const WorkItem* items);
 hipError_t launch_reduce(int grid, hipStream_t stream, const SolveDesc* descs,
                          const GroupItem* items);

@@ -99,12 +99,33 @@ constexpr int gram_red_doubles(int nb) {
   return most;
 }
 
+// A value the compiler must treat as unknown at this point (an empty asm that
+// claims to change it).  Applied per tile to the matrix base addresses and
+// sizes in the loops over tiles, so that the per-frame column addresses are
+// formed next to their use instead of being hoisted out of the loop and kept
+// live across it (NB columns of five matrices would not fit the scalar
+// registers).
+template <typename V>
+__device__ inline V opaque(V v) {
+  static_assert(sizeof(V) == 8, "64-bit values");
+  uint64_t u = __builtin_bit_cast(uint64_t, v);
+  // the values are uniform over the workgroup: keep them in scalar registers
+  uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+  uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+  asm volatile("" : "+s"(lo), "+s"(hi));
+  return __builtin_bit_cast(V, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 __device__ inline float clamp_sym(float v, float g) { return fminf(fmaxf(v, -g), g); }
 __device__ inline double clamp_sym(double v, double g) { return fmin(fmax(v, -g), g); }
 __device__ inline bool finite_val(float v) { return __builtin_isfinite(v); }
 __device__ inline bool finite_val(double v) { return __builtin_isfinite(v); }
 
-template <typename T, int NB, int MODE>
+// MT: the work item may span several tiles (the solve's tiles per work item,
+// d.tps).  The single-tile kernels (MT = false) keep their registers free of
+// the Gram accumulators during the loads and the rebuild, which decides
+// their occupancy; the loop costs about 40 registers.
+template <typename T, int NB, int MODE, bool MT>
 __global__ void __launch_bounds__(kThreads)
 k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
   constexpr bool INIT = MODE == 0;  // kModeInit
@@ -138,7 +159,6 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   const gptr<const T> Yin = as_global<T>(static_cast<const void*>(d.Y[(k + 1) & 1]));
   const gptr<T> Sout = as_global<T>(d.S[k & 1]);
   const gptr<T> Yout = as_global<T>(d.Y[k & 1]);
-  const cptr<T> P = as_const<T>(d.P);
   // S_0 = Y_0 = 0 are not read unless the solve starts from a given S0 / Y0
   const bool first = (k == 1) && !d.warm;
   T mu = 0, imu = 0, gam = 0;
@@ -164,87 +184,15 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
   for (int e = 0; e < 16; ++e) gacc[e] = 0.0;
   double r2 = 0.0, s1 = 0.0, s2 = 0.0, nf = 0.0;
 
-  {
-    // one tile per work item; row index within the solve (m < 2^30, so byte
-    // offsets fit 32 bits)
-    const uint32_t p = static_cast<uint32_t>(wi.slot) * kTile + tid;
-    const bool valid = p < m;
-    if constexpr (INIT) {
-#pragma unroll
-      for (int j = 0; j < NB4; ++j) {
-        T x = 0;
-        if (j < n && valid) x = (X + static_cast<size_t>(j) * m)[p];
-        const double xd = static_cast<double>(x);
-        s1 += fabs(xd);
-        s2 = fma(xd, xd, s2);
-        nf += finite_val(x) ? 0.0 : 1.0;
-        tileA[j * LDT + tid] = x;
-      }
-    } else if constexpr (WARM) {
-      // A_1 = X - S0 + Y0/mu; S0 and Y0 go to the buffers pass 1 reads
-      const gptr<const T> S0 = as_global<T>(d.S0);
-      const gptr<const T> Y0 = as_global<T>(d.Y0);
-      const gptr<T> S1 = as_global<T>(d.S[0]);
-      const gptr<T> Y1 = as_global<T>(d.Y[0]);
-#pragma unroll
-      for (int j = 0; j < NB4; ++j) {
-        T a = 0;
-        if (j < n && valid) {
-          const size_t col = static_cast<size_t>(j) * m;
-          const T x = (X + col)[p];
-          const T s = d.S0 ? (S0 + col)[p] : T(0);
-          const T y = d.Y0 ? (Y0 + col)[p] : T(0);
-          (S1 + col)[p] = s;
-          (Y1 + col)[p] = y;
-          a = fma(y, imu, x - s);
-        }
-        tileA[j * LDT + tid] = a;
-      }
-    } else {
-      T x[NB], y[NB], a[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        x[j] = 0; y[j] = 0; a[j] = 0;
-        if (j < n) {
-          if (valid) {
-            const size_t col = static_cast<size_t>(j) * m;
-            T s = 0;
-            x[j] = (X + col)[p];
-            if (!first) {
-              s = (Sin + col)[p];
-              y[j] = (Yin + col)[p];
-            }
-            a[j] = fma(y[j], imu, x[j] - s);
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NB4; ++j) {
-        T apj = 0;
-        if (j < NB && j < n) {
-          // Eq. 4 rebuild: l = sum_i a_i P_ij (P is zero outside n x n and
-          // exactly symmetric; row j of P is contiguous for scalar loads).
-          T l = 0;
-#pragma unroll
-          for (int i = 0; i < NB; ++i) l = fma(a[i], P[j * NB + i], l);
-          const T tt = fma(y[j], imu, x[j]) - l;          // X - L + Y/mu
-          const T sn = tt - clamp_sym(tt, gam);            // Eq. 5 shrink
-          const T z = (x[j] - l) - sn;                     // X - L - S
-          const T yn = fma(mu, z, y[j]);                   // Eq. 6
-          const double zd = static_cast<double>(z);
-          r2 = fma(zd, zd, r2);
-          apj = fma(yn, imu, x[j] - sn);                   // next X - S + Y/mu
-          if (valid) {
-            const size_t col = static_cast<size_t>(j) * m;
-            (Sout + col)[p] = sn;
-            (Yout + col)[p] = yn;
-          } else {
-            apj = 0;
-          }
-        }
-        tileA[j * LDT + tid] = apj;
-      }
-    }
+  // The work item's run of tiles: tiles [t0, t1) of kTile rows, walked in
+  // order; the Gram accumulators and scalars run over all of them, so the
+  // workgroup writes one partial.  Row index p within the solve (m < 2^30,
+  // so byte offsets fit 32 bits).
+  const int t0 = wi.slot * d.tps;
+  const int t1 = MT ? min(t0 + d.tps, d.tiles) : t0 + 1;
+  // Gram of the LDS tile (rows of this tile, A' frame-major), accumulated
+  // into this thread's 4x4 block over its row chunk.
+  auto gram_tile = [&]() {
     __syncthreads();
     if (gact) {
       const T* u = tileA + (4 * bi) * LDT;
@@ -263,6 +211,107 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
       }
     }
     __syncthreads();
+  };
+  if constexpr (INIT) {
+#pragma unroll 1
+    for (int tile = t0; tile < t1; ++tile) {
+      const uint32_t p = static_cast<uint32_t>(tile) * kTile + tid;
+      const bool valid = p < m;
+#pragma unroll
+      for (int j = 0; j < NB4; ++j) {
+        T x = 0;
+        if (j < n && valid) x = (X + static_cast<size_t>(j) * m)[p];
+        const double xd = static_cast<double>(x);
+        s1 += fabs(xd);
+        s2 = fma(xd, xd, s2);
+        nf += finite_val(x) ? 0.0 : 1.0;
+        tileA[j * LDT + tid] = x;
+      }
+      gram_tile();
+    }
+  } else if constexpr (WARM) {
+    // A_1 = X - S0 + Y0/mu; S0 and Y0 go to the buffers pass 1 reads
+    const gptr<const T> S0 = as_global<T>(d.S0);
+    const gptr<const T> Y0 = as_global<T>(d.Y0);
+    const gptr<T> S1 = as_global<T>(d.S[0]);
+    const gptr<T> Y1 = as_global<T>(d.Y[0]);
+#pragma unroll 1
+    for (int tile = t0; tile < t1; ++tile) {
+      const uint32_t p = static_cast<uint32_t>(tile) * kTile + tid;
+      const bool valid = p < m;
+#pragma unroll
+      for (int j = 0; j < NB4; ++j) {
+        T a = 0;
+        if (j < n && valid) {
+          const size_t col = static_cast<size_t>(j) * m;
+          const T x = (X + col)[p];
+          const T s = d.S0 ? (S0 + col)[p] : T(0);
+          const T y = d.Y0 ? (Y0 + col)[p] : T(0);
+          (S1 + col)[p] = s;
+          (Y1 + col)[p] = y;
+          a = fma(y, imu, x - s);
+        }
+        tileA[j * LDT + tid] = a;
+      }
+      gram_tile();
+    }
+  } else {
+#pragma unroll 1
+    for (int tile = t0; tile < t1; ++tile) {
+      const uint32_t p = static_cast<uint32_t>(tile) * kTile + tid;
+      const int64_t mt = opaque(m);
+      const bool valid = p < mt;
+      T x[NB], y[NB], a[NB];
+      {
+        const gptr<const T> Xt = opaque(X), St = opaque(Sin), Yt = opaque(Yin);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          x[j] = 0; y[j] = 0; a[j] = 0;
+          if (j < n && valid) {
+            const size_t col = static_cast<size_t>(j) * mt;
+            T s = 0;
+            x[j] = (Xt + col)[p];
+            if (!first) {
+              s = (St + col)[p];
+              y[j] = (Yt + col)[p];
+            }
+            a[j] = fma(y[j], imu, x[j] - s);
+          }
+        }
+      }
+      // The projector's address is made opaque to the compiler per tile, so
+      // its scalar loads stay inside the loop next to their uses instead of
+      // being hoisted (NB^2 values would not fit the scalar registers).
+      const cptr<T> P = as_const<T>(static_cast<const void*>(opaque(static_cast<const T*>(d.P))));
+      const gptr<T> So_t = opaque(Sout), Yo_t = opaque(Yout);
+#pragma unroll
+      for (int j = 0; j < NB4; ++j) {
+        T apj = 0;
+        if (j < NB && j < n) {
+          // Eq. 4 rebuild: l = sum_i a_i P_ij (P is zero outside n x n and
+          // exactly symmetric; row j of P is contiguous for scalar loads).
+          T l = 0;
+#pragma unroll
+          for (int i = 0; i < NB; ++i) l = fma(a[i], P[j * NB + i], l);
+          const T tt = fma(y[j], imu, x[j]) - l;          // X - L + Y/mu
+          const T sn_ = tt - clamp_sym(tt, gam);           // Eq. 5 shrink
+          const T z = (x[j] - l) - sn_;                    // X - L - S
+          const T yn_ = fma(mu, z, y[j]);                  // Eq. 6
+          const double zd = static_cast<double>(z);
+          r2 = fma(zd, zd, r2);
+          apj = fma(yn_, imu, x[j] - sn_);                 // next X - S + Y/mu
+          if (valid) {
+            const size_t col = static_cast<size_t>(j) * mt;
+            (So_t + col)[p] = sn_;
+            (Yo_t + col)[p] = yn_;
+          } else {
+            apj = 0;
+          }
+        }
+        tileA[j * LDT + tid] = apj;
+      }
+      gram_tile();
+    }
   }
 
 #ifdef RPCA_TRACE
@@ -318,7 +367,7 @@ k_stream(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items
 #endif
 }
 
-template <typename T, int NB>
+template <typename T, int NB, bool MT>
 __global__ void __launch_bounds__(kThreads)
 k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) {
   const int tid = threadIdx.x;
@@ -333,16 +382,18 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
   const gptr<const T> Sprev = as_global<T>(static_cast<const void*>(d.S[(k + 1) & 1]));
   const gptr<const T> Yprev = as_global<T>(static_cast<const void*>(d.Y[(k + 1) & 1]));
   const gptr<const T> Sk = as_global<T>(static_cast<const void*>(d.S[k & 1]));
-  const cptr<T> P = as_const<T>(d.P);
   const gptr<T> L = as_global<T>(d.Lout);
   const gptr<T> So = as_global<T>(d.Sout);
   const gptr<T> Yo = as_global<T>(d.Yout);
   const gptr<const T> Yk = as_global<T>(static_cast<const void*>(d.Y[k & 1]));
   const bool first = (k == 1) && !d.warm;
   const T imu = static_cast<T>(st->imu);
-  {
-    const uint32_t p = static_cast<uint32_t>(wi.slot) * kTile + tid;
-    if (p >= m) return;
+  const int t0 = wi.slot * d.tps;
+  const int t1 = MT ? min(t0 + d.tps, d.tiles) : t0 + 1;
+#pragma unroll 1
+  for (int tile = t0; tile < t1; ++tile) {
+    const uint32_t p = static_cast<uint32_t>(tile) * kTile + tid;
+    if (p >= m) break;
     if (k == 0) {  // sum|X| == 0: L = S = 0 (and Y = 0)
       for (int j = 0; j < n; ++j) {
         const size_t col = static_cast<size_t>(j) * m;
@@ -350,7 +401,7 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
         (So + col)[p] = T(0);
         if (d.Yout) (Yo + col)[p] = T(0);
       }
-      return;
+      continue;
     }
     T a[NB];
 #pragma unroll
@@ -367,6 +418,7 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
         a[j] = fma(y, imu, x - s);
       }
     }
+    const cptr<T> P = as_const<T>(static_cast<const void*>(opaque(static_cast<const T*>(d.P))));
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       if (j < n) {
@@ -380,6 +432,22 @@ k_finalize(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ ite
       }
     }
   }
+}
+
+// Launch one register class (dispatch helper of the instantiation units).
+template <typename T, int NB, bool MT>
+hipError_t launch_stream_class(int mode, int grid, hipStream_t stream, const SolveDesc* descs,
+                               const WorkItem* items) {
+  const dim3 g(grid), b(kThreads);
+  if (mode == kModeInit)
+    RPCA_LAUNCH((k_stream<T, NB, kModeInit, MT>), g, b, 0, stream, descs, items);
+  else if (mode == kModeUpdate)
+    RPCA_LAUNCH((k_stream<T, NB, kModeUpdate, MT>), g, b, 0, stream, descs, items);
+  else if (mode == kModeWarm)
+    RPCA_LAUNCH((k_stream<T, NB, kModeWarm, MT>), g, b, 0, stream, descs, items);
+  else
+    RPCA_LAUNCH((k_finalize<T, NB, MT>), g, b, 0, stream, descs, items);
+  return hipGetLastError();
 }
 
 }  // namespace rpca

@@ -212,6 +212,39 @@ int rpca_autotune(int32_t dtype, int64_t rows, void* stream) {
       if (rc < 0) return rc;
     }
   }
+  // 4. tiles per workgroup of the register kernel, per register class still
+  // on it (FP64: every class), timed on a `rows` x cls window
+  {
+    const int* cls_list = dtype == RPCA_F32 ? kClassesF32 : kClassesF64;
+    const int ncls = dtype == RPCA_F32 ? static_cast<int>(sizeof(kClassesF32) / sizeof(int))
+                                       : static_cast<int>(sizeof(kClassesF64) / sizeof(int));
+    for (int ci = 0; ci < ncls; ++ci) {
+      const int cls = cls_list[ci];
+      if (dtype == RPCA_F32 && rpca_tune_get(RPCA_KNOB_STREAM_KERNEL, dtype, cls) != 0) continue;
+      Bufs b;
+      rc = alloc_window(b, rows, cls, dtype, s);
+      if (rc != RPCA_OK) {
+        free_window(b);
+        return rc;
+      }
+      const int old = rpca_tune_get(RPCA_KNOB_REG_TILES, dtype, cls);
+      int best = old;
+      double best_ms = 1e30;
+      for (int tw : {1, 2, 4}) {
+        if (rpca_tune_set(RPCA_KNOB_REG_TILES, dtype, cls, tw) != RPCA_OK) continue;
+        double eig_ms = 0, upd_ms = 0;
+        rc = time_solve(b, rows, cls, dtype, kTuneIters, s, eig_ms, upd_ms);
+        if (rc < 0) break;
+        if (upd_ms < best_ms) {
+          best_ms = upd_ms;
+          best = tw;
+        }
+      }
+      (void)rpca_tune_set(RPCA_KNOB_REG_TILES, dtype, cls, rc < 0 ? old : best);
+      free_window(b);
+      if (rc < 0) return rc;
+    }
+  }
   return RPCA_OK;
 }
 
@@ -230,6 +263,12 @@ int rpca_autotune_save(const char* path) {
   for (int nb = 16; nb <= kEigHugeMaxN; nb += 16)
     std::fprintf(f, "%d %d %d %d\n", RPCA_KNOB_TILE_ROWS, RPCA_F32, nb,
                  rpca_tune_get(RPCA_KNOB_TILE_ROWS, RPCA_F32, nb));
+  for (int cls : kClassesF32)
+    std::fprintf(f, "%d %d %d %d\n", RPCA_KNOB_REG_TILES, RPCA_F32, cls,
+                 rpca_tune_get(RPCA_KNOB_REG_TILES, RPCA_F32, cls));
+  for (int cls : kClassesF64)
+    std::fprintf(f, "%d %d %d %d\n", RPCA_KNOB_REG_TILES, RPCA_F64, cls,
+                 rpca_tune_get(RPCA_KNOB_REG_TILES, RPCA_F64, cls));
   const int ok = std::fclose(f) == 0;
   return ok ? RPCA_OK : RPCA_ERR_ARG;
 }

@@ -6,10 +6,19 @@ iteration run in the library.
     srv.submit(M, tag=7, tol=1e-6, maxit=1000)   # M: device Casorati tensor
     for c in srv.step():                         # one quantum of iterations
         c.tag, c.status, c.iterations, c.L, c.S
+
+or, with futures and a background thread that steps the server:
+
+    srv = Server(dtype=RPCA_F32, background=True)
+    fut = srv.submit_async(frames)               # (n, H, W) stack or (m, n)
+    c = fut.result()                             # Completion with L and S
 """
 from __future__ import annotations
 
 import ctypes
+import itertools
+import threading
+from concurrent.futures import Future
 from dataclasses import dataclass
 from typing import Optional
 
@@ -38,7 +47,8 @@ class Server:
     iterations of every active solve together on the device."""
 
     def __init__(self, dtype: int = RPCA_F32, hbm_budget: int = 64 << 30, max_active: int = 64,
-                 quantum: int = 16, simulate: bool = False, stream: Optional[int] = None):
+                 quantum: int = 16, simulate: bool = False, stream: Optional[int] = None,
+                 background: bool = False):
         lib = _lib.load()
         if stream is None and not simulate:
             import torch
@@ -54,6 +64,15 @@ class Server:
         self._buf = (RpcaCompletion * self._cap)()
         self._live = {}  # tag -> (M, L, S) kept alive until completion
         self._timeout = 0.0
+        self._futures = {}  # tag -> Future of submit_async
+        self._mu = threading.RLock()
+        self._tags = itertools.count(1 << 62)  # tags of submit_async
+        self._wake = threading.Event()
+        self._stop = False
+        self._thread = None
+        if background:
+            self._thread = threading.Thread(target=self._loop, name="rpca-server", daemon=True)
+            self._thread.start()
 
     def set_timeout(self, seconds: float) -> None:
         """Timeout given to the requests submitted from now on (0 = none)."""
@@ -69,9 +88,10 @@ class Server:
     def submit_raw(self, problem, tag: int, keep=None) -> int:
         """Queue an rpca_problem whose device buffers the caller owns.  The
         library rejects a tag that names a request not yet reported."""
-        rc = self._lib.rpca_server_submit(self._h, ctypes.byref(problem), int(tag))
-        if rc == 0:
-            self._live[int(tag)] = keep
+        with self._mu:
+            rc = self._lib.rpca_server_submit(self._h, ctypes.byref(problem), int(tag))
+            if rc == 0:
+                self._live[int(tag)] = keep
         return int(rc)
 
     def submit(self, M, tag: int, lam: Optional[float] = None, mu: Optional[float] = None,
@@ -82,8 +102,9 @@ class Server:
         `timeout` (seconds) overrides the server's timeout for this request."""
         import torch
         from . import _problem, _check_device, _dtype_code
-        if int(tag) in self._live:
-            raise ValueError(f"tag {tag} names a request that has not been reported")
+        with self._mu:
+            if int(tag) in self._live:
+                raise ValueError(f"tag {tag} names a request that has not been reported")
         if _dtype_code(M) != self._dtype:
             raise ValueError("M's dtype differs from the server's dtype")
         _check_device(M)
@@ -100,20 +121,69 @@ class Server:
         if rc != 0:
             raise ValueError(f"request rejected: {rc}")
 
+    def submit_async(self, frames, lam: Optional[float] = None, mu: Optional[float] = None,
+                     tol: float = 1e-6, maxit: int = 1000, timeout: Optional[float] = None) -> Future:
+        """Queue a window (an (n, H, W) frame stack or an (m, n) Casorati
+        tensor on the device) and return a Future that step() (or the
+        background thread) resolves with its Completion."""
+        fut = Future()
+        with self._mu:
+            tag = next(self._tags)
+            self._futures[tag] = fut
+            try:
+                self.submit(frames, tag, lam=lam, mu=mu, tol=tol, maxit=maxit, timeout=timeout)
+            except BaseException:
+                self._futures.pop(tag, None)
+                raise
+        self._wake.set()
+        return fut
+
     def step(self) -> list:
-        n = ctypes.c_int32(0)
-        rc = self._lib.rpca_server_step(self._h, self._buf, self._cap, ctypes.byref(n))
-        out = []
-        for i in range(n.value):
-            c = self._buf[i]
-            keep = self._live.pop(int(c.tag), None)
-            L = S = None
-            if keep is not None and len(keep) == 3:
-                L, S = keep[1], keep[2]
-            out.append(Completion(int(c.tag), int(c.status), int(c.iterations), float(c.residual), L, S))
-        if rc < 0:
-            raise RuntimeError(f"server step failed ({rc}): {self._lib.rpca_last_error().decode()}")
-        return out
+        with self._mu:
+            n = ctypes.c_int32(0)
+            rc = self._lib.rpca_server_step(self._h, self._buf, self._cap, ctypes.byref(n))
+            out = []
+            for i in range(n.value):
+                c = self._buf[i]
+                keep = self._live.pop(int(c.tag), None)
+                L = S = None
+                if keep is not None and len(keep) == 3:
+                    L, S = keep[1], keep[2]
+                out.append(Completion(int(c.tag), int(c.status), int(c.iterations), float(c.residual), L, S))
+            err = None
+            if rc < 0:
+                err = RuntimeError(f"server step failed ({rc}): {self._lib.rpca_last_error().decode()}")
+            futs, plain = [], []
+            for c in out:
+                f = self._futures.pop(c.tag, None)
+                (plain if f is None else futs).append(c if f is None else (f, c))
+        for fut, c in futs:
+            fut.set_result(c)
+        if err is not None:
+            raise err
+        return plain
+
+    def _loop(self):
+        """Background stepping: run quanta while requests are pending, sleep
+        until the next submit_async otherwise."""
+        while not self._stop:
+            try:
+                left = self.pending()[0]
+            except Exception:
+                break
+            if left == 0:
+                self._wake.wait(0.05)
+                self._wake.clear()
+                continue
+            try:
+                self.step()
+            except Exception as e:  # a device failure: fail every waiting future
+                with self._mu:
+                    futs = list(self._futures.values())
+                    self._futures.clear()
+                for f in futs:
+                    f.set_exception(e)
+                break
 
     def pending(self) -> tuple[int, int, int, int]:
         """(not yet reported, queued, active, admitted bytes)."""
@@ -125,10 +195,21 @@ class Server:
         return int(self._lib.rpca_server_peak_bytes(self._h))
 
     def close(self) -> None:
-        if self._h:
-            self._lib.rpca_server_destroy(self._h)
-            self._h = None
-            self._live.clear()
+        self._stop = True
+        self._wake.set()
+        if self._thread is not None and self._thread is not threading.current_thread():
+            self._thread.join()
+        self._thread = None
+        with self._mu:
+            if self._h:
+                self._lib.rpca_server_destroy(self._h)
+                self._h = None
+                self._live.clear()
+            futs = list(self._futures.values())
+            self._futures.clear()
+        for f in futs:
+            if not f.done():
+                f.cancel()
 
     def __del__(self):
         try:

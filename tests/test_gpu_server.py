@@ -94,3 +94,22 @@ def test_server_fp32_matches_oracle():
     report("server_vs_oracle", relL=eL, relS=eS, it=c.iterations, it_ref=ref.iterations)
     assert eL <= 1e-4 and eS <= 1e-4
     assert abs(c.iterations - ref.iterations) <= 1
+
+
+def test_submit_async_background_bitwise_alone():
+    """Futures from a server stepped by its background thread: each result is
+    bitwise the window solved alone."""
+    import torch
+    device()
+    wins = _windows(np.float32)[:5]
+    alone = {i: rp.solve(M, tol=1e-6, maxit=300) for i, M in wins}
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=3, quantum=8, background=True)
+    futs = {i: srv.submit_async(M, tol=1e-6, maxit=300) for i, M in wins}
+    got = {i: f.result(timeout=120) for i, f in futs.items()}
+    srv.close()
+    torch.cuda.synchronize()
+    for i, r in alone.items():
+        c = got[i]
+        assert c.status == r.status and c.iterations == r.iterations
+        assert torch.equal(c.L, r.L) and torch.equal(c.S, r.S)
+    report("server_async", requests=len(got))

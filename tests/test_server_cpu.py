@@ -183,3 +183,47 @@ def test_python_submit_checks():
         srv.submit(M32, tag=4)
     assert srv.pending()[1] == 1
     srv.close()
+
+
+def _future_request(srv, p):
+    """What Server.submit_async does once its device checks passed (the
+    simulated server takes placeholder addresses instead of tensors)."""
+    import concurrent.futures
+    fut = concurrent.futures.Future()
+    with srv._mu:
+        tag = next(srv._tags)
+        srv._futures[tag] = fut
+        assert srv.submit_raw(p, tag) == 0
+    srv._wake.set()
+    return fut
+
+
+def test_submit_async_futures_resolve_on_step():
+    """A future-backed request is resolved by the step that reports it;
+    requests submitted with plain tags are returned by step()."""
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=4, quantum=8, simulate=True)
+    srv.submit_raw(_prob(4096, 20, 16, 1 << 36), 5)
+    futs = [_future_request(srv, _prob(4096, 10, 8 * (i + 1), (i + 2) << 36)) for i in range(3)]
+    plain = []
+    for _ in range(10):
+        plain += srv.step()
+    assert [c.tag for c in plain] == [5]
+    assert all(f.done() for f in futs)
+    assert [f.result().iterations for f in futs] == [8, 16, 24]
+    srv.close()
+
+
+def test_background_server_resolves_futures_and_closes():
+    import concurrent.futures
+    import time
+    srv = Server(rp.RPCA_F32, hbm_budget=1 << 40, max_active=2, quantum=4, simulate=True,
+                 background=True)
+    futs = [_future_request(srv, _prob(4096, 10, 4 * (i + 1), (i + 1) << 36)) for i in range(5)]
+    done, _ = concurrent.futures.wait(futs, timeout=30)
+    assert len(done) == 5
+    assert sorted(f.result().iterations for f in futs) == [4, 8, 12, 16, 20]
+    # a request still running when the server closes gets its future cancelled
+    fut = _future_request(srv, _prob(4096, 10, 10 ** 6, 9 << 36))
+    time.sleep(0.05)
+    srv.close()
+    assert fut.cancelled()
