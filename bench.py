@@ -422,6 +422,8 @@ def run_serve(args):
         equal += int(fingerprint(r.L) == fL and fingerprint(r.S) == fS and
                      r.iterations == iters[tag] and r.status == status[tag])
         del r, M
+        if checked % 50 == 0:
+            print(f"[serve] bitwise check: {equal} of {checked} equal so far", file=sys.stderr, flush=True)
     print(f"[serve] bitwise check: {equal} of {checked} equal", file=sys.stderr, flush=True)
 
     # a sustainable arrival rate: server and plain path on the same trace
@@ -688,7 +690,7 @@ def run_frames132(args):
                    "maxit": maxit, "iterations": iters},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_wide<144,kModeUpdate,fp32>",
+                     "kernel": "k_wide<float, 144, 1, 0>",
                      "bytes_per_launch": bytes_per_launch, "mean_launch_us": upd_ms * 1e3,
                      "launches": prof["update_launches"],
                      "measured_on": "one repeated solve, each launch recording its own HIP "
@@ -840,12 +842,16 @@ def main():
     # Which update kernel ran: the register kernel of the 20-frame class, or
     # the MFMA tile kernel (32-frame tile) when the tuner chose it for that
     # class.  The committed counter summary covers the register kernel only.
-    tiled = args.dtype == "f32" and 20 in tuning_summary()["tile_kernel_classes"]
+    # Names as rocprofv3 prints them: k_stream<T, NB, MODE, MT> (MODE 1 =
+    # update, MT = several tiles per workgroup), k_wide<T, NB, MODE, PREC>.
+    ts = tuning_summary()
+    tiled = args.dtype == "f32" and 20 in ts["tile_kernel_classes"]
     if tiled:
-        kname, traffic = "k_wide<32,kModeUpdate,fp32>", None
+        kname, traffic = "k_wide<float, 32, 1, 0>", None
     else:
-        kname = f"k_stream<{'float' if args.dtype == 'f32' else 'double'},20,kModeUpdate>"
-        traffic = measured_traffic() if args.dtype == "f32" else None
+        mt = ts[f"reg_tiles_{args.dtype}"].get("20", 1) > 1
+        kname = f"k_stream<{'float' if args.dtype == 'f32' else 'double'}, 20, 1, {'true' if mt else 'false'}>"
+        traffic = measured_traffic() if args.dtype == "f32" and not mt else None
     lat = np.array(times) * 1e3
     wbytes = 4 if args.dtype == "f32" else 8
     per_iter_gbs = value * 5 * wbytes / 1e9
