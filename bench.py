@@ -276,15 +276,21 @@ def fingerprint(t) -> int:
     return int((v * w).sum())
 
 
-def serve_trace_run(reqs, args, plain: bool, check_every: int):
+def serve_trace_run(reqs, args, plain: bool, check_every: int, prebuilt=None):
     """Serve `reqs` [(t, side, n, seed)] as they arrive, through the server
     (or, plain=True, one rp.solve per request in arrival order).  Arrived
     requests wait in a client-side FIFO in front of the server's own queue,
-    which is kept a few requests deep; a request's window is built on the
-    device when it is handed over (its latency counts from its arrival), so
-    the device holds the inputs of the admitted and the few queued requests
-    only.  Returns the completion times, statuses, iterations and, for every
-    check_every-th request, a fingerprint of L and S."""
+    which is kept a few requests deep; latency counts from arrival.  The
+    input windows are `prebuilt` (device tensors in arrival order), or are
+    built ahead of their arrival, at most 16 windows ahead, so that building
+    them does not hold up the server: the host-side draws of a window (up to
+    a few tenths of a second of Python for the largest) run in a process
+    pool, and a producer thread renders them on a stream of its own.  Returns the completion times, statuses,
+    iterations and, for every check_every-th request, a fingerprint of L and
+    S."""
+    import queue
+    import threading
+
     import torch
 
     import paper_2506_10257_amd as rp
@@ -298,6 +304,58 @@ def serve_trace_run(reqs, args, plain: bool, check_every: int):
         _, side, n, seed = reqs[i]
         return device_window(side, side, n, seed, dev).view(n, side * side).t()
 
+    halt = threading.Event()
+    producer = None
+    if prebuilt is not None:
+        def take(i, block=True):
+            return prebuilt[i]
+    else:
+        # host-side draws in worker processes (submitted in order, at most 64
+        # ahead), device rendering in this thread on a stream of its own
+        from concurrent.futures import ProcessPoolExecutor
+        from synth.device import render_window, window_geometry
+
+        ready = queue.Queue(maxsize=16)
+        side = torch.cuda.Stream(device=dev)
+        pool = ProcessPoolExecutor(min(16, len(os.sched_getaffinity(0))))
+
+        def produce():
+            try:
+                futs = {}
+                with torch.cuda.stream(side):
+                    for i in range(len(reqs)):
+                        for k in range(i, min(i + 64, len(reqs))):
+                            if k not in futs:
+                                _, sd, nn, seed = reqs[k]
+                                futs[k] = pool.submit(window_geometry, sd, sd, nn, seed)
+                        _, sd, nn, _ = reqs[i]
+                        M = render_window(futs.pop(i).result(), dev).view(nn, sd * sd).t()
+                        side.synchronize()
+                        while True:
+                            if halt.is_set():
+                                return
+                            try:
+                                ready.put((i, M), timeout=0.5)
+                                break
+                            except queue.Full:
+                                pass
+            except BaseException as e:  # handed to the consumer, which raises it
+                ready.put((-1, e))
+
+        producer = threading.Thread(target=produce, name="window-producer", daemon=True)
+        producer.start()
+
+        def take(i, block=True):
+            """Window i, or None when block is False and it is not built yet."""
+            try:
+                j, M = ready.get(block=block)
+            except queue.Empty:
+                return None
+            if j < 0:
+                raise M
+            assert j == i, (j, i)
+            return M
+
     done_at, iters, status, fps = {}, {}, {}, {}
 
     def record(tag, st, it, L, S, t_done):
@@ -310,43 +368,53 @@ def serve_trace_run(reqs, args, plain: bool, check_every: int):
     t0 = time.perf_counter()
     note = 10.0
     peak = 0
-    if plain:
-        for k, (t, _, _, _) in enumerate(reqs):
-            now = time.perf_counter() - t0
-            if now >= note:
-                print(f"[serve] plain {now:.0f} s: {k} of {len(reqs)} done", file=sys.stderr, flush=True)
-                note += 10.0
-            if now < t:
-                time.sleep(t - now)
-            r = rp.solve(build(k), tol=tol, maxit=maxit)
-            torch.cuda.synchronize()
-            record(k, r.status, r.iterations, r.L, r.S, time.perf_counter() - t0)
-            del r
-    else:
-        srv = Server(rp.RPCA_F32, hbm_budget=int(args.budget_gb * (1 << 30)),
-                     max_active=args.max_active, quantum=args.quantum)
-        nxt = 0  # next request to hand to the server
-        while len(done_at) < len(reqs):
-            now = time.perf_counter() - t0
-            if now >= note:
-                print(f"[serve] {now:.0f} s: {len(done_at)} of {len(reqs)} done, "
-                      f"{nxt} handed over", file=sys.stderr, flush=True)
-                note += 10.0
-            _, queued, _, _ = srv.pending()
-            while nxt < len(reqs) and reqs[nxt][0] <= now and queued < 8:
-                srv.submit(build(nxt), tag=nxt, tol=tol, maxit=maxit)
-                nxt += 1
-                queued += 1
-            left, _, _, _ = srv.pending()
-            if left == 0:
-                if nxt < len(reqs):
-                    time.sleep(max(0.0, reqs[nxt][0] - (time.perf_counter() - t0)))
-                continue
-            for c in srv.step():
-                record(c.tag, c.status, c.iterations, c.L, c.S, time.perf_counter() - t0)
-                c.L = c.S = None
-        peak = srv.peak_bytes()
-        srv.close()
+    try:
+        if plain:
+            for k, (t, _, _, _) in enumerate(reqs):
+                now = time.perf_counter() - t0
+                if now >= note:
+                    print(f"[serve] plain {now:.0f} s: {k} of {len(reqs)} done", file=sys.stderr, flush=True)
+                    note += 10.0
+                if now < t:
+                    time.sleep(t - now)
+                r = rp.solve(take(k), tol=tol, maxit=maxit)
+                torch.cuda.synchronize()
+                record(k, r.status, r.iterations, r.L, r.S, time.perf_counter() - t0)
+                del r
+        else:
+            srv = Server(rp.RPCA_F32, hbm_budget=int(args.budget_gb * (1 << 30)),
+                         max_active=args.max_active, quantum=args.quantum)
+            nxt = 0  # next request to hand to the server
+            while len(done_at) < len(reqs):
+                now = time.perf_counter() - t0
+                if now >= note:
+                    print(f"[serve] {now:.0f} s: {len(done_at)} of {len(reqs)} done, "
+                          f"{nxt} handed over", file=sys.stderr, flush=True)
+                    note += 10.0
+                left, queued, _, _ = srv.pending()
+                while nxt < len(reqs) and reqs[nxt][0] <= now and queued < 8:
+                    # with work in the server, a window not built yet waits for the next step
+                    M = take(nxt, block=left == 0)
+                    if M is None:
+                        break
+                    srv.submit(M, tag=nxt, tol=tol, maxit=maxit)
+                    nxt += 1
+                    queued += 1
+                    left += 1
+                if left == 0:
+                    if nxt < len(reqs):
+                        time.sleep(max(0.0, reqs[nxt][0] - (time.perf_counter() - t0)))
+                    continue
+                for c in srv.step():
+                    record(c.tag, c.status, c.iterations, c.L, c.S, time.perf_counter() - t0)
+                    c.L = c.S = None
+            peak = srv.peak_bytes()
+            srv.close()
+    finally:
+        halt.set()
+        if producer is not None:
+            producer.join()
+            pool.shutdown(cancel_futures=True)
     wall = time.perf_counter() - t0
     return done_at, iters, status, fps, wall, peak
 
@@ -369,13 +437,17 @@ def run_serve(args):
     """Poisson arrivals of square windows (256-1024 px sides, 10/20/40/100
     frames, FP32, tol 1e-6, maxit 1000) served by the continuous-batching
     server.  Two parts:
-      * the full trace at args.rate for args.duration s through the server;
-        every args.check_every-th served result is compared bit for bit with
-        the same window solved alone (plain path);
-      * a sustainable arrival rate (args.sustain_rate), where the latency
-        measures service rather than queueing, through the server and
-        through the plain path (one solve per call, first come first
-        served) on the same trace.
+      * the full trace at args.rate for args.duration s through the server
+        (its windows built ahead of arrival by a producer thread, so the
+        client's input generation does not hold the server up); every
+        args.check_every-th served result is compared bit for bit with the
+        same window solved alone (plain path);
+      * a sustainable arrival rate (args.sustain_rate, 3 req/s by default,
+        about 60% of what the server completes on this mix), where the
+        server's latency measures service rather than queueing, through the
+        server and through the plain path (one solve per call, first come
+        first served) on the same trace, with every window built before the
+        clock starts; --sustain-only runs this part alone.
     The plain path is not run on the full trace: at its capacity (about a
     third of the server's) the 60 s trace would take the better part of an
     hour."""
@@ -405,39 +477,48 @@ def run_serve(args):
     rp.solve(w0, tol=1e-6, maxit=5)
     torch.cuda.synchronize()
 
-    done_at, iters, status, fps, wall, peak = serve_trace_run(reqs, args, False, args.check_every)
-    full = serve_summary(reqs, done_at, iters, status, wall)
-    full["peak_admitted_gb"] = peak / 2 ** 30
-    print(f"[serve] full trace: {full['solves_per_s']:.2f} solves/s, p99 {full['latency_ms']['p99']:.0f} ms",
-          file=sys.stderr, flush=True)
+    full, checked, equal = None, 0, 0
+    if not args.sustain_only:
+        done_at, iters, status, fps, wall, peak = serve_trace_run(reqs, args, False, args.check_every)
+        full = serve_summary(reqs, done_at, iters, status, wall)
+        full["peak_admitted_gb"] = peak / 2 ** 30
+        print(f"[serve] full trace: {full['solves_per_s']:.2f} solves/s, p99 {full['latency_ms']['p99']:.0f} ms",
+              file=sys.stderr, flush=True)
 
-    # bitwise check of the sampled served results against the same windows alone
-    from synth.device import device_window as dw
-    checked = equal = 0
-    for tag, (fL, fS) in sorted(fps.items()):
-        _, side, n, seed = reqs[tag]
-        M = dw(side, side, n, seed, torch.device("cuda:0")).view(n, side * side).t()
-        r = rp.solve(M, tol=1e-6, maxit=1000)
-        checked += 1
-        equal += int(fingerprint(r.L) == fL and fingerprint(r.S) == fS and
-                     r.iterations == iters[tag] and r.status == status[tag])
-        del r, M
-        if checked % 50 == 0:
-            print(f"[serve] bitwise check: {equal} of {checked} equal so far", file=sys.stderr, flush=True)
-    print(f"[serve] bitwise check: {equal} of {checked} equal", file=sys.stderr, flush=True)
+        # bitwise check of the sampled served results against the same windows alone
+        from synth.device import device_window as dw
+        checked = equal = 0
+        for tag, (fL, fS) in sorted(fps.items()):
+            _, side, n, seed = reqs[tag]
+            M = dw(side, side, n, seed, torch.device("cuda:0")).view(n, side * side).t()
+            r = rp.solve(M, tol=1e-6, maxit=1000)
+            checked += 1
+            equal += int(fingerprint(r.L) == fL and fingerprint(r.S) == fS and
+                         r.iterations == iters[tag] and r.status == status[tag])
+            del r, M
+            if checked % 50 == 0:
+                print(f"[serve] bitwise check: {equal} of {checked} equal so far", file=sys.stderr, flush=True)
+        print(f"[serve] bitwise check: {equal} of {checked} equal", file=sys.stderr, flush=True)
 
     # a sustainable arrival rate: server and plain path on the same trace
+    # (its windows are built before the clock starts, so the latencies are
+    # those of the server and of the plain path alone)
     sreqs = trace_of(args.sustain_rate, args.sustain_duration, 6)
-    d2, i2, s2, _, w2, p2 = serve_trace_run(sreqs, args, False, 0)
+    dev = torch.device("cuda:0")
+    swin = [device_window(side, side, n, seed, dev).view(n, side * side).t()
+            for (_, side, n, seed) in sreqs]
+    torch.cuda.synchronize()
+    d2, i2, s2, _, w2, p2 = serve_trace_run(sreqs, args, False, 0, prebuilt=swin)
     sus = serve_summary(sreqs, d2, i2, s2, w2)
-    d3, i3, s3, _, w3, _ = serve_trace_run(sreqs, args, True, 0)
+    d3, i3, s3, _, w3, _ = serve_trace_run(sreqs, args, True, 0, prebuilt=swin)
+    del swin
     sus_plain = serve_summary(sreqs, d3, i3, s3, w3)
     out = {
         "metric": METRIC,
-        "value": full["value"],
+        "value": full["value"] if full else sus["value"],
         "unit": "pixel-frames/s per ALM iter",
-        "n_gpus": 1, "steps": len(reqs), "warmup": 1,
-        "ms_per_step": full["wall_s"] / len(reqs) * 1e3,
+        "n_gpus": 1, "steps": len(reqs if full else sreqs), "warmup": 1,
+        "ms_per_step": (full or sus)["wall_s"] / len(reqs if full else sreqs) * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (Poisson arrivals; square windows 256..1024 px, device-built "
                 "ultrasound-shaped frames)",
@@ -735,10 +816,12 @@ def main():
     ap.add_argument("--duration", type=float, default=60.0, help="serve: trace length (s)")
     ap.add_argument("--check-every", type=int, default=10,
                     help="serve: every k-th served result is compared bit for bit with the window solved alone")
-    ap.add_argument("--sustain-rate", type=float, default=5.0,
+    ap.add_argument("--sustain-rate", type=float, default=3.0,
                     help="serve: arrival rate of the second, sustainable-rate trace")
     ap.add_argument("--sustain-duration", type=float, default=40.0,
                     help="serve: length of the sustainable-rate trace (s)")
+    ap.add_argument("--sustain-only", action="store_true",
+                    help="serve: run only the sustainable-rate trace (server and plain path)")
     ap.add_argument("--serve-frames", default="10,20,40,100", help="serve: allowed frame counts")
     ap.add_argument("--max-active", type=int, default=48, help="serve: active solves at most")
     ap.add_argument("--quantum", type=int, default=16, help="serve: iterations per step")

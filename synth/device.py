@@ -62,31 +62,17 @@ def _splat_many(img_flat, H: int, W: int, frame_idx: np.ndarray, cy: np.ndarray,
     img_flat.index_put_((idx[ok],), val[ok], accumulate=True)
 
 
-def device_window(H: int, W: int, n: int, seed: int, device, dtype=None, snr_db: float = 20.0):
-    """(n, H, W) C-contiguous window on `device` (the Casorati layout with
-    m = H*W), densities as for the batched and served sets."""
-    import torch
-    dtype = dtype or torch.float32
+def window_geometry(H: int, W: int, n: int, seed: int) -> dict:
+    """The host-side draws of a window (drift phases, bound bubble centres,
+    free bubble tracks along the vessel paths), from numpy with the window's
+    seed, in the order ``device_window`` has always drawn them.  Plain
+    arrays, so it can run in a worker process."""
     n_bound, n_free, n_vessels = density_counts(H, W)
     rng = np.random.default_rng(seed)
-    gen = torch.Generator(device=device)
-    gen.manual_seed(int(seed))
-    ghat = _gauss_hat(H, W, device)
-    s1 = _speckle(gen, H, W, ghat, device)
-    s2 = _speckle(gen, H, W, ghat, device)
     phi1, phi2 = rng.uniform(0, 2 * np.pi, size=2)
-    t = torch.arange(n, device=device, dtype=torch.float64)
-    c1 = 1.0 + DRIFT * torch.sin(2 * math.pi * t / (4 * n) + phi1)
-    c2 = DRIFT * torch.cos(2 * math.pi * t / (4 * n) + phi2)
-    clean = c1[:, None, None] * s1[None] + c2[:, None, None] * s2[None]
-
     lo = 4.0
     by = rng.uniform(lo, H - lo, size=n_bound)
     bx = rng.uniform(lo, W - lo, size=n_bound)
-    bound = torch.zeros(H * W, device=device, dtype=torch.float64)
-    _splat_many(bound, H, W, np.zeros(n_bound, dtype=np.int64), by, bx, BUBBLE_AMPLITUDE, device)
-    clean += bound.view(1, H, W)
-
     paths = [_vessel_path(rng, H, W) for _ in range(max(n_vessels, 1))]
     fy, fx, ff = [], [], []
     k = np.arange(n, dtype=np.float64)
@@ -104,11 +90,44 @@ def device_window(H: int, W: int, n: int, seed: int, device, dtype=None, snr_db:
         fy.append(pos[:, 0])
         fx.append(pos[:, 1])
         ff.append(np.arange(n, dtype=np.int64))
-    if n_free:
+    cat = (lambda a, dt: np.concatenate(a) if a else np.zeros(0, dtype=dt))
+    return {"H": H, "W": W, "n": n, "seed": seed, "phi": (float(phi1), float(phi2)),
+            "by": by, "bx": bx, "fy": cat(fy, np.float64), "fx": cat(fx, np.float64),
+            "ff": cat(ff, np.int64)}
+
+
+def render_window(geom: dict, device, dtype=None, snr_db: float = 20.0):
+    """(n, H, W) C-contiguous window on `device` from its host-side draws:
+    speckle and noise from a device generator seeded with the window's seed,
+    bubbles splatted at the drawn positions."""
+    import torch
+    dtype = dtype or torch.float32
+    H, W, n, seed = geom["H"], geom["W"], geom["n"], geom["seed"]
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    ghat = _gauss_hat(H, W, device)
+    s1 = _speckle(gen, H, W, ghat, device)
+    s2 = _speckle(gen, H, W, ghat, device)
+    phi1, phi2 = geom["phi"]
+    t = torch.arange(n, device=device, dtype=torch.float64)
+    c1 = 1.0 + DRIFT * torch.sin(2 * math.pi * t / (4 * n) + phi1)
+    c2 = DRIFT * torch.cos(2 * math.pi * t / (4 * n) + phi2)
+    clean = c1[:, None, None] * s1[None] + c2[:, None, None] * s2[None]
+
+    by, bx = geom["by"], geom["bx"]
+    bound = torch.zeros(H * W, device=device, dtype=torch.float64)
+    _splat_many(bound, H, W, np.zeros(len(by), dtype=np.int64), by, bx, BUBBLE_AMPLITUDE, device)
+    clean += bound.view(1, H, W)
+    if len(geom["ff"]):
         flat = clean.view(-1)
-        _splat_many(flat, H, W, np.concatenate(ff), np.concatenate(fy), np.concatenate(fx),
-                    BUBBLE_AMPLITUDE, device)
+        _splat_many(flat, H, W, geom["ff"], geom["fy"], geom["fx"], BUBBLE_AMPLITUDE, device)
     rms = float(torch.sqrt(torch.mean(clean * clean)))
     sigma_n = rms * 10.0 ** (-snr_db / 20.0)
     clean += sigma_n * torch.randn(clean.shape, generator=gen, device=device, dtype=torch.float64)
     return clean.to(dtype).contiguous()
+
+
+def device_window(H: int, W: int, n: int, seed: int, device, dtype=None, snr_db: float = 20.0):
+    """(n, H, W) C-contiguous window on `device` (the Casorati layout with
+    m = H*W), densities as for the batched and served sets."""
+    return render_window(window_geometry(H, W, n, seed), device, dtype, snr_db)

@@ -64,3 +64,24 @@ def test_serve_trace_poisson():
     t = np.array([a for a, *_ in tr])
     assert np.all(np.diff(t) > 0) and t[-1] < 60.0
     assert all(s in SERVE_SIDES and n in SERVE_FRAMES for _, s, n, _ in tr)
+
+
+def test_device_window_geometry_in_worker_processes():
+    """The serve workload draws a window's host-side geometry in worker
+    processes and renders it in the main process: the result is the window
+    built in one piece, bit for bit (CPU device here)."""
+    import pickle
+    from concurrent.futures import ProcessPoolExecutor
+
+    import torch
+    from synth.device import device_window, render_window, window_geometry
+
+    shapes = [(40, 52, 20, 5001), (64, 48, 10, 5002), (24, 24, 3, 5003)]
+    with ProcessPoolExecutor(2) as ex:
+        geoms = list(ex.map(window_geometry, *zip(*shapes)))
+    for (H, W, n, seed), g in zip(shapes, geoms):
+        pickle.dumps(g)
+        a = render_window(g, torch.device("cpu"))
+        b = device_window(H, W, n, seed, torch.device("cpu"))
+        assert a.shape == (n, H, W)
+        assert torch.equal(a, b)
