@@ -340,7 +340,12 @@ def serve_trace_run(reqs, args, plain: bool, check_every: int, prebuilt=None):
                             except queue.Full:
                                 pass
             except BaseException as e:  # handed to the consumer, which raises it
-                ready.put((-1, e))
+                while not halt.is_set():
+                    try:
+                        ready.put((-1, e), timeout=0.5)
+                        break
+                    except queue.Full:
+                        pass
 
         producer = threading.Thread(target=produce, name="window-producer", daemon=True)
         producer.start()
