@@ -717,31 +717,57 @@ namespace {
     }                                             \
   } while (0)
 
-// Streams, events and pinned state buffers of the calls made by one host
-// thread on one device: created on the first call, reused by later calls
-// (their creation costs more than a small solve), never destroyed (process
-// exit releases them).
+// Streams, events and pinned state buffers for the calls on one device.  A
+// call leases an idle set (created when none is idle; creating one costs
+// more than a small solve) and gives it back when it returns, after its
+// last synchronisation, so a set is never used by two calls at once.  The
+// pool holds as many sets as calls ever ran at once on the device, whatever
+// the number of host threads that made them; the sets live until the
+// process ends.
 struct LaneCache {
   Lanes L;
-  bool ok = false;
 };
-thread_local LaneCache* t_lane_cache[64] = {};
+std::mutex g_lane_pool_mu;
+std::vector<LaneCache*> g_lane_pool[64];
 
-// A view of the first `nlanes` lanes of this thread's cached set for `dev`
-// with room for `count` solve states, or an error code.
-int cached_lanes(int dev, int nlanes, int count, Lanes& view) {
+struct LaneLease {
+  int dev = -1;
+  LaneCache* c = nullptr;
+  LaneLease() = default;
+  LaneLease(const LaneLease&) = delete;
+  LaneLease& operator=(const LaneLease&) = delete;
+  ~LaneLease() {
+    if (c) {
+      std::lock_guard<std::mutex> lk(g_lane_pool_mu);
+      g_lane_pool[dev].push_back(c);
+    }
+  }
+};
+
+// Lease a lane set of device `dev` (current) into `lease` and return a view
+// of its first `nlanes` lanes with room for `count` solve states in `view`,
+// or an error code.
+int lease_lanes(int dev, int nlanes, int count, LaneLease& lease, Lanes& view) {
   if (dev < 0 || dev >= 64) return RPCA_ERR_DEVICE;
-  LaneCache*& c = t_lane_cache[dev];
-  if (c == nullptr) c = new LaneCache();
-  if (!c->ok) {
-    lanes_destroy(c->L);
+  LaneCache* c = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_lane_pool_mu);
+    if (!g_lane_pool[dev].empty()) {
+      c = g_lane_pool[dev].back();
+      g_lane_pool[dev].pop_back();
+    }
+  }
+  if (c == nullptr) {
+    c = new LaneCache();
     const int rc = lanes_create(c->L, kMaxLanes);
     if (rc != RPCA_OK) {
       lanes_destroy(c->L);
+      delete c;
       return rc;
     }
-    c->ok = true;
   }
+  lease.dev = dev;
+  lease.c = c;
   const int rc = lanes_reserve_pinned(c->L, count);
   if (rc != RPCA_OK) return rc;
   view = Lanes{};
@@ -790,6 +816,7 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   const bool use_graph = !prof && !graphs_disabled();
   int rc = RPCA_OK;
   char* arena = nullptr;
+  LaneLease lease;  // returns the lane set when the call returns
   Lanes L;
   Plan plan;
   std::vector<EvPair> evs;
@@ -803,7 +830,7 @@ int run_batch(rpca_problem* probs, int count, int dtype, int gram_mode, hipStrea
   }
   assign_lanes(ptrs, nlanes);
 
-  rc = cached_lanes(dev, nlanes, count, L);
+  rc = lease_lanes(dev, nlanes, count, lease, L);
   if (rc != RPCA_OK) return rc;
   hipStream_t s0 = L.s[0];
   if (prof) t_evs = &evs;
@@ -980,7 +1007,8 @@ done:
     if (arena) (void)hipFreeAsync(arena, L.s[0]);
     (void)hipStreamSynchronize(L.s[0]);
   }
-  // L is a view of the thread's cached lanes: nothing to destroy
+  // L is a view of the leased lane set, which the lease gives back (every
+  // lane was synchronised above): nothing to destroy
   return rc;
 }
 

@@ -44,3 +44,40 @@ def test_batch_matches_oracle_fp32():
                it_ref=ref.iterations, relL=relL, relS=relS)
         assert abs(r.iterations - ref.iterations) <= 1
         assert relL <= 1e-4 and relS <= 1e-4
+
+
+def test_concurrent_host_threads_bitwise_equal_alone():
+    """Calls from several host threads at once each lease their own streams,
+    events and state buffers: every result is bitwise the one the same window
+    gets solved alone, and a second wave of threads (new threads, the same
+    sets reused) gives the same results again."""
+    import threading
+    import torch
+    wins = [batch_window(H, W, n, 7200 + i) for i, (H, W, n) in enumerate(SHAPES)]
+    Xs = [w.X().astype(np.float32) for w in wins]
+    alone = [gpu_solve(X, np.float32, tol=1e-6, maxit=300) for X in Xs]
+    Ms = [to_dev(X, np.float32) for X in Xs]
+    torch.cuda.synchronize()
+    for wave in range(2):
+        out = [None] * len(Ms)
+        errs = []
+
+        def work(i):
+            try:
+                r = rp.solve(Ms[i], tol=1e-6, maxit=300)
+                torch.cuda.synchronize()
+                out[i] = r
+            except BaseException as e:  # reported by the main thread
+                errs.append(e)
+
+        ts = [threading.Thread(target=work, args=(i,)) for i in range(len(Ms))]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join(timeout=120)
+        assert not errs, errs
+        for i, (r, (L, S, it, rc, _)) in enumerate(zip(out, alone)):
+            same = torch.equal(L, r.L) and torch.equal(S, r.S)
+            report("threads-vs-alone", wave=wave, case=i, it=r.iterations, it_alone=it, bitwise=int(same))
+            assert r.iterations == it and r.status == rc
+            assert same
