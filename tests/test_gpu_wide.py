@@ -177,8 +177,8 @@ def test_bf16x6_meets_fp32_bar(H, W, n):
 # the f64 matrix cores) and, above 64 frames, the in-place eigensolver with a
 # Newton-Schulz re-orthonormalisation of its warm start.  Held to the FP64
 # bar: 1e-10 in L and S with the same iteration count and status.
-FP64_WIDE = [(48, 50, 40), (40, 41, 60), (36, 30, 64), (40, 44, 65), (44, 50, 100),
-             (40, 37, 112), (36, 40, 113), (32, 41, 128)]
+FP64_WIDE = [(40, 38, 33), (48, 50, 40), (40, 41, 60), (36, 30, 64), (40, 44, 65), (36, 44, 81),
+             (40, 40, 96), (38, 40, 97), (44, 50, 100), (40, 37, 112), (36, 40, 113), (32, 41, 128)]
 
 
 def _solve64(X, tol=1e-7, maxit=300):
@@ -198,7 +198,7 @@ def test_wide_fp64_matches_oracle(H, W, n):
     assert rc == ref.status
 
 
-@pytest.mark.parametrize("n", [60, 100, 128])
+@pytest.mark.parametrize("n", [33, 60, 96, 100, 128])
 @pytest.mark.parametrize("k", [1, 2, 7])
 def test_wide_fp64_iterate_parity(n, k):
     """k-th iterate (tol = 0); k >= 2 runs the warm start with the
