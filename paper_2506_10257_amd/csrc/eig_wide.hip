@@ -15,9 +15,16 @@
 //   * V is kept in full; row i of V J depends only on row i, so each thread
 //     owns (row, pair) items and overwrites V[i][p], V[i][q].  Up to 112
 //     frames V sits in LDS beside G; in the 144-frame class (packed G alone
-//     takes 83.5 KB) it stays in the solve's V buffer in global memory,
-//     where it is rotated in place (the barriers of each round order the
-//     accesses, and the 166 KB stay in L2);
+//     takes 83.5 KB) it stays in the solve's V buffer in global memory.
+//     FP64 solves, and FP32 solves of more than 136 frames, rotate it there
+//     in place (the barriers of each round order the accesses, and the
+//     166 KB stay in L2).  Warm-started FP32 solves of up to 136 frames
+//     leave V fixed during the sweeps and accumulate the rotations as an
+//     increment D in LDS, in FP32 (V J_1 J_2 ... = V (I + D)); each rotation
+//     adds terms of the size of its angle to D, so D's rounding shrinks with
+//     the angles as the iteration settles.  One product V <- V + V D on the
+//     f64 matrix cores ends the eigensolve.  The cold start, whose rotations
+//     build all of V, rotates V in place;
 //   * a round is [apply the round's rotations] barrier [the first wave
 //     computes the next round's rotations from the updated G] barrier.
 //
@@ -25,10 +32,11 @@
 // step's eigenvectors V, on G~ = V^T G V, which is nearly diagonal once the
 // iteration settles.  The two products run on the f64 matrix cores
 // (W = G V goes through a per-solve global scratch buffer, since LDS holds G
-// and V already).  For FP64 solves V is first brought back to orthogonality
-// by one Newton-Schulz step V <- V (3I - V^T V) / 2 (also on the matrix
-// cores); for FP32 solves the rounding of the rotations stays far below the
-// FP32 rounding of the data and the step is skipped.  With V in global
+// and V already).  For FP64 solves, and for FP32 solves that accumulate an
+// FP32 increment, V is first brought back to orthogonality by one
+// Newton-Schulz step V <- V (3I - V^T V) / 2 (also on the matrix cores); for
+// the other FP32 solves the rounding of the FP64 rotations stays far below
+// the FP32 rounding of the data and the step is skipped.  With V in global
 // memory the projector P = V diag(w) V^T is also formed on the f64 matrix
 // cores.
 #include <type_traits>
@@ -51,6 +59,11 @@ template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT)
 k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   constexpr bool VG = NMAX > kEigWideMaxN;  // V in global memory
+  // FP32 solves of up to kEigIncMaxN frames in the device-memory class keep
+  // V fixed during the sweeps and accumulate the sweeps' rotations as an
+  // increment D (V J_1 J_2 ... = V (I + D)) in LDS, in FP32
+  constexpr bool VI = VG && std::is_same<T, float>::value;
+  constexpr int LDD = kEigIncMaxN + 1;
   constexpr int NPK = NMAX * (NMAX + 1) / 2;
   constexpr int LDV = NMAX + 1;
   constexpr int NPM = NMAX / 2;                               // pairs per round at most
@@ -59,6 +72,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   static_assert(NMAX % 2 == 0, "even class size");
   __shared__ double Gp[NPK];
   __shared__ double Vs[VG ? 1 : NMAX * LDV];
+  __shared__ float Ds[VI ? kEigIncMaxN * LDD : 1];
   __shared__ int tp[NPM], tq[NPM];
   __shared__ double tc[NPM], ts[NPM], tdt[NPM];
   __shared__ double w[NMAX];
@@ -70,6 +84,21 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   const SolveDesc& d = descs[ids[blockIdx.x]];
   SolveState* st = d.st;
   if (st->done) return;
+#ifdef RPCA_TRACE
+  int64_t tprev = RPCA_NOW();
+#define EIG_MARK(i)                               \
+  do {                                            \
+    if (tid == 0) {                               \
+      const int64_t tnow_ = RPCA_NOW();           \
+      st->trace[i] += tnow_ - tprev;              \
+      tprev = tnow_;                              \
+    }                                             \
+  } while (0)
+#else
+#define EIG_MARK(i) \
+  do {              \
+  } while (0)
+#endif
   const int n = d.n;
   const int nb = d.nb;
   const int kd = st->iter;
@@ -81,6 +110,9 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   }
 
   const bool warm = kd > 0;
+  // (warm starts only: the cold start's rotations build all of V, and D
+  // would be of order one)
+  const bool vinc = VI && warm && n <= kEigIncMaxN;
   // V rows: LDS (stride LDV) or the solve's V buffer (stride nb, nb x nb,
   // zero outside n x n)
   const gptr<double> Vg = as_global<double>(static_cast<void*>(d.V));
@@ -92,6 +124,8 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
         Vg[idx] = (i == j && i < n) ? 1.0 : 0.0;
       }
     }
+    if (vinc)
+      for (int idx = tid; idx < kEigIncMaxN * LDD; idx += NT) Ds[idx] = 0.0f;
   } else {
     for (int idx = tid; idx < NMAX * LDV; idx += NT) {
       const int i = idx / LDV, j = idx - (idx / LDV) * LDV;
@@ -143,6 +177,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   }
   __syncthreads();
   if (!s_go) return;
+  EIG_MARK(0);
   const double tau = s_tau;
 
   if (warm) {
@@ -159,9 +194,10 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     const gptr<double> Wg = as_global<double>(static_cast<void*>(d.escratch));
     // with V in global memory the products stop at nb (V is nb x nb)
     const int nt16 = VG ? nb / 16 : NT16;
-    if constexpr (std::is_same<T, double>::value) {
-      // FP64 solves: one Newton-Schulz step V <- V (3I - V^T V) / 2 first, so
-      // the rounding of the rotations does not accumulate over the solve.
+    if (std::is_same<T, double>::value || vinc) {
+      // FP64 solves, and FP32 solves that accumulate an FP32 increment: one
+      // Newton-Schulz step V <- V (3I - V^T V) / 2 first, so the rounding of
+      // the rotations does not accumulate over the solve.
       // C = V^T V goes to the scratch; each wave keeps its blocks of V C in
       // registers until every wave has read V, then writes its entries of
       // the new V (each entry has one owner).
@@ -263,6 +299,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     __syncthreads();
   }
 
+  EIG_MARK(1);
   const int N2 = n + (n & 1);
   const int M = N2 - 1;
   const int NP = N2 / 2;
@@ -369,7 +406,39 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
         }
       }
       constexpr int VC = 4;  // V rows read together
-      if (vact && ts[vk] != 0.0) {
+      if (vinc) {
+        // D <- D J + (J - I) for the pair's plane rotation J, with J - I
+        // written through c - 1 and s, so every term added to D is of the
+        // size of the rotation angle and the FP32 rounding scales with it
+        if (vact && ts[vk] != 0.0) {
+          const float sk = static_cast<float>(ts[vk]);
+          const float cm = static_cast<float>(tc[vk] - 1.0);
+          const int p = tp[vk], qq = tq[vk];
+          for (int i0 = vr0; i0 < n; i0 += VC * vrs) {
+            float dp[VC], dq[VC];
+#pragma unroll
+            for (int u = 0; u < VC; ++u) {
+              const int i = i0 + u * vrs;
+              dp[u] = 0.0f;
+              dq[u] = 0.0f;
+              if (i < n) {
+                dp[u] = Ds[i * LDD + p];
+                dq[u] = Ds[i * LDD + qq];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < VC; ++u) {
+              const int i = i0 + u * vrs;
+              if (i < n) {
+                const float ep = (i == p ? cm : 0.0f) - (i == qq ? sk : 0.0f);
+                const float eq = (i == p ? sk : 0.0f) + (i == qq ? cm : 0.0f);
+                Ds[i * LDD + p] = dp[u] + (fmaf(cm, dp[u], -sk * dq[u]) + ep);
+                Ds[i * LDD + qq] = dq[u] + (fmaf(sk, dp[u], cm * dq[u]) + eq);
+              }
+            }
+          }
+        }
+      } else if (vact && ts[vk] != 0.0) {
         const double sk = ts[vk], ck = tc[vk];
         const int p = tp[vk], qq = tq[vk];
         for (int i0 = vr0; i0 < n; i0 += VC * vrs) {
@@ -412,6 +481,50 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
       if (r + 1 < M) make_round(r + 1);
       __syncthreads();
     }
+  }
+
+  EIG_MARK(2);
+  if (vinc && sweeps > 0) {
+    // V <- V + V D on the f64 matrix cores; each wave keeps its 16 x 16
+    // blocks in registers until every wave has read V, then adds them to its
+    // entries of V (each entry has one owner)
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int NWV = NT / 64;
+    constexpr int NT16 = NMAX / 16;
+    constexpr int MV = (NT16 * NT16 + NWV - 1) / NWV;
+    const int wv = tid >> 6, l = tid & 63;
+    const int nt16 = nb / 16;
+    d4 vd[MV];
+#pragma unroll
+    for (int q = 0; q < MV; ++q) {
+      const int t = wv + q * NWV;
+      vd[q] = d4{0.0, 0.0, 0.0, 0.0};
+      if (t < nt16 * nt16) {
+        const int bi = t / nt16, bj = t - (t / nt16) * nt16;
+        const int j = 16 * bj + (l & 15);
+#pragma unroll 4
+        for (int kk = 0; kk < nt16 * 4; ++kk) {
+          const int kq = 4 * kk + (l >> 4);
+          const double a = Vg[(16 * bi + (l & 15)) * nb + kq];
+          const double b = (kq < n && j < n) ? static_cast<double>(Ds[kq * LDD + j]) : 0.0;
+          vd[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, vd[q], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MV; ++q) {
+      const int t = wv + q * NWV;
+      if (t < nt16 * nt16) {
+        const int bi = t / nt16, bj = t - (t / nt16) * nt16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * bi + (l >> 4) + 4 * r, j = 16 * bj + (l & 15);
+          Vg[i * nb + j] = Vg[i * nb + j] + vd[q][r];
+        }
+      }
+    }
+    __syncthreads();
   }
 
   // SVT weights and P = V diag(w) V^T (exactly symmetric), in storage precision.
@@ -471,6 +584,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
       d.V[idx] = (i < n && j < n) ? Vs[i * LDV + j] : 0.0;
     }
   }
+  EIG_MARK(3);
   if (tid == 0) {
     int rank = 0;
     for (int k = 0; k < n; ++k) rank += w[k] != 0.0 ? 1 : 0;
@@ -479,6 +593,7 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     st->sweeps_total += sweeps;
     st->iter = kd + 1;
   }
+#undef EIG_MARK
 }
 
 }  // namespace
