@@ -53,7 +53,8 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
   __shared__ double G0s[NMAX * LD], G1s[NMAX * LD];  // two copies of G
   __shared__ double V0s[NMAX * LD], V1s[NMAX * LD];  // two copies of V
   __shared__ int cu[2][NMAX];
-  __shared__ double ca[2][NMAX], cb[2][NMAX], cd[2][NMAX];
+  __shared__ double2 cab[2][NMAX];
+  __shared__ double cd[2][NMAX];
   __shared__ double w[NMAX];
   __shared__ double scal[kScalars];
   __shared__ int s_go;
@@ -257,13 +258,12 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
     double* Vn = SRC ? V0s : V1s;
     const int rb = r & 1;
     const int* tu_ = cu[rb];
-    const double* ta = ca[rb];
-    const double* tb = cb[rb];
+    const double2* tab = cab[rb];
     const double* td = cd[rb];
 #pragma unroll
     for (int q = 0; q < MU; ++q) {
       if (tid + q * NT < nup) {  // slots past n(n+1)/2 are skipped by whole waves
-        const double v = rotated_entry<LD>(ui[q], uj[q], Gc, tu_, ta, tb, td);
+        const double v = rotated_entry<LD>(ui[q], uj[q], Gc, tu_, tab, td);
         Gn[ui[q] * LD + uj[q]] = v;
         Gn[uj[q] * LD + ui[q]] = v;
       }
@@ -273,7 +273,8 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
       if (tid + q * NT < nfull) {
         const int j = fc[q], i = fr[q];
         const int pj = tu_[j];
-        Vn[i * LD + j] = fma(ta[j], Vc[i * LD + (pj & 0xff)], tb[j] * Vc[i * LD + ((pj >> 8) & 0xff)]);
+        const double2 abj = tab[j];
+        Vn[i * LD + j] = fma(abj.x, Vc[i * LD + (pj & 0xff)], abj.y * Vc[i * LD + ((pj >> 8) & 0xff)]);
       }
     }
     const int kp = tid - (NT - 64);
@@ -282,12 +283,12 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
       pair_indices(r + 1, kp, N2, p, q);
       double c = 1.0, s = 0.0, dt = 0.0;
       if (q < n) {
-        const double gpp = rotated_entry<LD>(p, p, Gc, tu_, ta, tb, td);
-        const double gqq = rotated_entry<LD>(q, q, Gc, tu_, ta, tb, td);
-        const double gpq = rotated_entry<LD>(p, q, Gc, tu_, ta, tb, td);
+        const double gpp = rotated_entry<LD>(p, p, Gc, tu_, tab, td);
+        const double gqq = rotated_entry<LD>(q, q, Gc, tu_, tab, td);
+        const double gpq = rotated_entry<LD>(p, q, Gc, tu_, tab, td);
         make_rotation<T>(gpp, gqq, gpq, c, s, dt);
       }
-      set_pair_columns(p, q, n, c, s, dt, cu[rb ^ 1], ca[rb ^ 1], cb[rb ^ 1], cd[rb ^ 1]);
+      set_pair_columns(p, q, n, c, s, dt, cu[rb ^ 1], cab[rb ^ 1], cd[rb ^ 1]);
     }
     __syncthreads();
   };
@@ -307,7 +308,7 @@ k_eig(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids) {
       pair_indices(0, tid, N2, p, q);
       double c = 1.0, s = 0.0, dt = 0.0;
       if (q < n) make_rotation<T>(G[p * LD + p], G[q * LD + q], G[p * LD + q], c, s, dt);
-      set_pair_columns(p, q, n, c, s, dt, cu[0], ca[0], cb[0], cd[0]);
+      set_pair_columns(p, q, n, c, s, dt, cu[0], cab[0], cd[0]);
     }
     if (!__syncthreads_or(need)) break;
     for (int r = 0; r < M; ++r) {

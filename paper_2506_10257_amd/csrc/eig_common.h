@@ -48,37 +48,36 @@ __device__ inline void pair_indices(int r, int k, int N2, int& p, int& q) {
 
 // Per-round column table of J, written by the threads that compute the
 // round's rotations: for index i, column i of J is a_i e_u + b_i e_v with
-// (u, v) the pair containing i, packed as u | v << 8 | rotated << 16, and
-// dg_i the exact shift of the diagonal entry g_ii (-t g_pq for p, +t g_pq
-// for q).  An index paired with the padding index gets the identity column.
+// (u, v) the pair containing i, packed as u | v << 8 | rotated << 16, (a_i,
+// b_i) stored together (one 16-byte read), and dg_i the exact shift of the
+// diagonal entry g_ii (-t g_pq for p, +t g_pq for q).  An index paired with
+// the padding index gets the identity column.
 __device__ inline void set_pair_columns(int p, int q, int n, double c, double s, double dt,
-                                        int* cu, double* ca, double* cb, double* cd) {
+                                        int* cu, double2* cab, double* cd) {
   if (q >= n) {
     cu[p] = p | (p << 8);
-    ca[p] = 1.0;
-    cb[p] = 0.0;
+    cab[p] = make_double2(1.0, 0.0);
     cd[p] = 0.0;
     return;
   }
   const int packed = p | (q << 8) | (s != 0.0 ? (1 << 16) : 0);
   cu[p] = packed;
-  ca[p] = c;
-  cb[p] = -s;
+  cab[p] = make_double2(c, -s);
   cd[p] = -dt;
   cu[q] = packed;
-  ca[q] = s;
-  cb[q] = c;
+  cab[q] = make_double2(s, c);
   cd[q] = dt;
 }
 
 // Entry (i, j) of J^T G J from the column table (G with leading dimension LD).
 template <int LD>
 __device__ inline double rotated_entry(int i, int j, const double* G, const int* cu,
-                                       const double* ca, const double* cb, const double* cd) {
+                                       const double2* cab, const double* cd) {
   const int pi = cu[i], pj = cu[j];
   const int ui = pi & 0xff, vi = (pi >> 8) & 0xff;
   const int uj = pj & 0xff, vj = (pj >> 8) & 0xff;
-  const double ai = ca[i], bi = cb[i], aj = ca[j], bj = cb[j];
+  const double2 abi = cab[i], abj = cab[j];
+  const double ai = abi.x, bi = abi.y, aj = abj.x, bj = abj.y;
   double gen = ai * aj * G[ui * LD + uj];
   gen = fma(ai * bj, G[ui * LD + vj], gen);
   gen = fma(bi * aj, G[vi * LD + uj], gen);

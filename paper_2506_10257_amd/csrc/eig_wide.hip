@@ -73,8 +73,9 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
   __shared__ double Gp[NPK];
   __shared__ double Vs[VG ? 1 : NMAX * LDV];
   __shared__ float Ds[VI ? kEigIncMaxN * LDD : 1];
-  __shared__ int tp[NPM], tq[NPM];
-  __shared__ double tc[NPM], ts[NPM], tdt[NPM];
+  __shared__ int tpq[NPM];      // p | q << 8
+  __shared__ double2 tcs[NPM];  // (c, s): one 16-byte read per pair
+  __shared__ double tdt[NPM];
   __shared__ double w[NMAX];
   __shared__ double scal[kScalars];
   __shared__ int s_go;
@@ -317,13 +318,16 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
     }
     bk[q] = (b < nblk2 ? b - k2 * (k2 + 1) / 2 : 0) | (k2 << 8);
   }
-  // V items: thread tid rotates pair vk = tid mod NP of rows vr0, vr0 + vrs,
-  // ... (vrs = NT / NP threads share a pair), so it reads its pair's rotation
-  // once per round
+  // V items: a thread rotates one pair vk (its rotation read once per round)
+  // in rows vr0, vr0 + vrs, ... (vrs = NT / NP threads share a pair).  In LDS
+  // the threads of a pair are consecutive and take consecutive rows, so the
+  // lanes of a wave hit distinct banks; in device memory consecutive threads
+  // take consecutive pairs of one row, which touches fewer cache lines.
   const int vrs = NP > 0 ? NT / NP : 1;
-  const int vk = NP > 0 ? tid % NP : 0;
-  const int vr0 = NP > 0 ? tid / NP : n;
-  const bool vact = NP > 0 && vr0 < vrs;
+  const bool vlds = !VG || vinc;
+  const int vk = NP > 0 ? (vlds ? tid / vrs : tid % NP) : 0;
+  const int vr0 = NP > 0 ? (vlds ? tid - (tid / vrs) * vrs : tid / NP) : n;
+  const bool vact = NP > 0 && (vlds ? vk < NP : vr0 < vrs);
 
   // Rotations of round r for pairs handled by the first wave.
   auto make_round = [&](int r) {
@@ -332,10 +336,8 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
       pair_indices(r, tid, N2, p, q);
       double c = 1.0, s = 0.0, dt = 0.0;
       if (q < n) make_rotation<T>(Gp[pk(p, p)], Gp[pk(q, q)], Gp[pk(p, q)], c, s, dt);
-      tp[tid] = p;
-      tq[tid] = q;
-      tc[tid] = c;
-      ts[tid] = s;
+      tpq[tid] = p | (q << 8);
+      tcs[tid] = make_double2(c, s);
       tdt[tid] = dt;
     }
   };
@@ -363,8 +365,9 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
         gmode[q] = 0;
         if (tid + q * NT < nblk2) {
           const int k1 = bk[q] & 0xff, k2 = bk[q] >> 8;
-          const int p1 = tp[k1], q1 = tq[k1], p2 = tp[k2], q2 = tq[k2];
-          const double s1 = ts[k1], s2 = ts[k2];
+          const int pq1 = tpq[k1], pq2 = tpq[k2];
+          const int p1 = pq1 & 0xff, q1 = pq1 >> 8, p2 = pq2 & 0xff, q2 = pq2 >> 8;
+          const double s1 = tcs[k1].y, s2 = tcs[k2].y;
           if (k1 == k2) {
             if (s1 != 0.0) {
               gmode[q] = 1;
@@ -394,7 +397,8 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
           Gp[gi[q][2]] = 0.0;
         } else if (gmode[q] == 2) {
           const int k1 = bk[q] & 0xff, k2 = bk[q] >> 8;
-          const double c1 = tc[k1], s1 = ts[k1], c2 = tc[k2], s2 = ts[k2];
+          const double2 cs1 = tcs[k1], cs2 = tcs[k2];
+          const double c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
           const double b_pp = gv[q][0], b_pq = gv[q][1], b_qp = gv[q][2], b_qq = gv[q][3];
           // T = B J2 (columns p2, q2), then J1^T T (rows p1, q1)
           const double t_pp = fma(c2, b_pp, -s2 * b_pq), t_pq = fma(s2, b_pp, c2 * b_pq);
@@ -410,10 +414,12 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
         // D <- D J + (J - I) for the pair's plane rotation J, with J - I
         // written through c - 1 and s, so every term added to D is of the
         // size of the rotation angle and the FP32 rounding scales with it
-        if (vact && ts[vk] != 0.0) {
-          const float sk = static_cast<float>(ts[vk]);
-          const float cm = static_cast<float>(tc[vk] - 1.0);
-          const int p = tp[vk], qq = tq[vk];
+        const double2 csk = vact ? tcs[vk] : make_double2(1.0, 0.0);
+        if (csk.y != 0.0) {
+          const float sk = static_cast<float>(csk.y);
+          const float cm = static_cast<float>(csk.x - 1.0);
+          const int pqk = tpq[vk];
+          const int p = pqk & 0xff, qq = pqk >> 8;
           for (int i0 = vr0; i0 < n; i0 += VC * vrs) {
             float dp[VC], dq[VC];
 #pragma unroll
@@ -438,9 +444,11 @@ k_eig_wide(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ ids)
             }
           }
         }
-      } else if (vact && ts[vk] != 0.0) {
-        const double sk = ts[vk], ck = tc[vk];
-        const int p = tp[vk], qq = tq[vk];
+      } else if (vact && tcs[vk].y != 0.0) {
+        const double2 csk = tcs[vk];
+        const double sk = csk.y, ck = csk.x;
+        const int pqk = tpq[vk];
+        const int p = pqk & 0xff, qq = pqk >> 8;
         for (int i0 = vr0; i0 < n; i0 += VC * vrs) {
           double vp[VC], vq[VC];
 #pragma unroll
