@@ -16,7 +16,6 @@ constexpr int kGroup = 32;         // partial slots per first-level reduction gr
 constexpr int kEigMaxN = 64;       // frame count handled by the double-buffered eigensolver
 constexpr int kEigWideMaxN = 112;  // frame count handled by the in-place eigensolver (V in LDS)
 constexpr int kEigHugeMaxN = 144;  // ... and by its variant with V in global memory
-constexpr int kEigIncMaxN = 136;   // FP32 solves of that class whose rotations accumulate in LDS
 constexpr int kF64MaxN = 128;      // largest frame count of FP64 solves (tile kernel classes to 128)
 constexpr int kEigWideThreads = 1024;
 constexpr int kWideRows = 64;      // pixel rows per tile of the MFMA streaming kernel

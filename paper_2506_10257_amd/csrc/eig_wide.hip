@@ -50,6 +50,10 @@ namespace {
 
 using namespace eigk;
 
+// FP32 solves of the device-memory class up to this many frames accumulate
+// their rotations as an FP32 increment in LDS (74.5 KB beside packed G).
+constexpr int kEigIncMaxN = 136;
+
 __device__ inline int pk(int i, int j) {  // packed upper index, i <= j
   return j * (j + 1) / 2 + i;
 }
