@@ -105,8 +105,10 @@ def test_zero_input_wide():
 def test_wide_batch_bitwise_equals_alone():
     import torch
     device()
+    # 113 and 132 frames take the eigensolver's FP32 increment path, 140 the
+    # in-place path, in the same 144-frame eigensolve launch
     shapes = [(40, 40, 100), (32, 48, 20), (48, 40, 80), (30, 30, 112), (64, 64, 10), (40, 44, 132),
-              (36, 36, 113)]
+              (36, 36, 113), (36, 40, 140)]
     Ms = [to_dev(batch_window(H, W, n, 7300 + i).X(), np.float32) for i, (H, W, n) in enumerate(shapes)]
     alone = [rp.solve(M, tol=1e-6, maxit=200) for M in Ms]
     many = rp.solve_many(Ms, tol=1e-6, maxit=200)
