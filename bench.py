@@ -776,6 +776,8 @@ def run_frames132(args):
                    "maxit": maxit, "iterations": iters},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "per_iteration_achieved": m * n * sum(iters) / wall * 20.0 / 1e9,
+                     "per_iteration_frac": m * n * sum(iters) / wall * 20.0 / (HBM_PEAK_GBS * 1e9),
                      "kernel": "k_wide<float, 144, 1, 0>",
                      "bytes_per_launch": bytes_per_launch, "mean_launch_us": upd_ms * 1e3,
                      "launches": prof["update_launches"],
