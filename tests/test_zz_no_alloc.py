@@ -7,7 +7,7 @@ import pytest
 
 import paper_2506_10257_amd as rp
 from oracle import rpca, rel_fro
-from synth import window_512x512x20, planted_low_rank_sparse
+from synth import window_512x512x20, planted_low_rank_sparse, batch_window
 from tests.gpu_helpers import to_dev, to_host, report, device
 
 pytestmark = pytest.mark.gpu
@@ -52,6 +52,37 @@ def test_noalloc_equals_allocating_call(dtype):
     report("noalloc small vs oracle", relL=relL, relS=relS, it=it2, it_ref=ref.iterations)
     assert relL <= bar and relS <= bar
     assert abs(it2 - ref.iterations) <= (0 if dtype == np.float64 else 1)
+
+
+# Wide windows: the in-place eigensolver with V in the workspace (and, for
+# FP32 solves of 113-136 frames, its FP32 increment path and scratch), two
+# calls in a row, the second smaller.
+@pytest.mark.parametrize("dtype,shapes", [
+    (np.float32, [(48, 40, 132), (40, 40, 100)]),
+    (np.float64, [(40, 40, 128), (36, 40, 100)]),
+])
+def test_noalloc_wide_classes_equal_allocating_call(dtype, shapes):
+    import torch
+    device()
+    code = rp.RPCA_F32 if dtype == np.float32 else rp.RPCA_F64
+    alloc_fn = rp.rpca_solve_f32 if dtype == np.float32 else rp.rpca_solve_f64
+    tol = 1e-6 if dtype == np.float32 else 1e-9
+    for H, W, n in shapes:
+        X = batch_window(H, W, n, 8100 + n).X().astype(dtype)
+        m = X.shape[0]
+        M = to_dev(X, dtype)
+        L1, S1 = torch.empty_like(M), torch.empty_like(M)
+        rc1, it1 = alloc_fn(M, m, n, -1.0, -1.0, tol, 80, L1, S1)
+        L2 = torch.full_like(M, float("nan"))
+        S2 = torch.full_like(M, float("nan"))
+        torch.cuda.synchronize()
+        rc2, it2 = rp.rpca_solve_noalloc(M, m, n, code, -1.0, -1.0, tol, 80, L2, S2)
+        torch.cuda.synchronize()
+        same = torch.equal(L1, L2) and torch.equal(S1, S2)
+        report(f"noalloc wide {H}x{W}x{n}", dtype=np.dtype(dtype).name, rc=rc2, rc_alloc=rc1,
+               it=it2, it_alloc=it1, bitwise=int(same))
+        assert rc2 == rc1 and it2 == it1
+        assert same
 
 
 def test_noalloc_too_large_is_rejected():
