@@ -59,9 +59,11 @@ def test_warm_start_matches_oracle(dtype, which):
 
 
 @pytest.mark.parametrize("n,gram_mode", [(40, rp.RPCA_GRAM_DEFAULT), (100, rp.RPCA_GRAM_DEFAULT),
-                                         (20, rp.RPCA_GRAM_BF16X6)])
+                                         (132, rp.RPCA_GRAM_DEFAULT), (20, rp.RPCA_GRAM_BF16X6)])
 def test_warm_start_tile_kernel_classes(n, gram_mode):
-    """Warm starts through the MFMA tile kernel (40, 100 frames; BF16x6)."""
+    """Warm starts through the MFMA tile kernel (40, 100, 132 frames; BF16x6);
+    at 132 frames the eigensolver's FP32 increment path from the second
+    iteration on."""
     device()
     X, S0, Y0 = _sliding(40, 44, n, 10, 9100 + n)
     ref = rpca(X, tol=1e-6, maxit=2000, S0=S0, Y0=Y0)
