@@ -139,6 +139,12 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   __shared__ T At[NBK * LDA];
   __shared__ float Lt[REB && !F64 ? NB * LDA : 1];
   __shared__ double wred[NW][kScalars];
+  // FP64 96-frame class: the projector rows in LDS instead of registers
+  // (48 registers per lane that the update pass would otherwise spill;
+  // 73.7 KB beside the 62.2 KB A tile).  Larger FP64 classes do not fit.
+  constexpr bool PL = F64 && NB == 96 && REB;
+  constexpr int LDP = NB + 1;
+  __shared__ T Ps[PL ? NB * LDP : 1];
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
@@ -188,7 +194,7 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
   constexpr int NREP = XTRA ? 1 : NW / NT16;
   const int own_t[2] = {XTRA ? w : w % NT16, NW + (w >> 2)};
   const bool owns[2] = {XTRA || w < NT16 * NREP, XTRA && w < 4 * (NT16 - NW)};
-  T pa[PREC ? 1 : NOWN][PREC ? 1 : NK4];
+  T pa[PREC || PL ? 1 : NOWN][PREC || PL ? 1 : NK4];
   bf8 ph[PREC ? NOWN : 1][PREC ? NKB : 1], pl[PREC ? NOWN : 1][PREC ? NKB : 1];
   bf8 pm[X6 ? NOWN : 1][X6 ? NKB : 1];
   if constexpr (REB) {
@@ -198,8 +204,10 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
       const int t = own_t[o];
       const int prow = 16 * (owns[o] ? t : 0) + (l & 15);
       if constexpr (PREC == 0) {
+        if constexpr (!PL) {
 #pragma unroll
-        for (int kk = 0; kk < NK4; ++kk) pa[o][kk] = P[prow * NB + 4 * kk + (l >> 4)];
+          for (int kk = 0; kk < NK4; ++kk) pa[o][kk] = P[prow * NB + 4 * kk + (l >> 4)];
+        }
       } else {
 #pragma unroll
         for (int kk = 0; kk < NKB; ++kk) {
@@ -218,6 +226,10 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
     }
   }
 
+  if constexpr (PL) {  // read by the rebuild after the first tile's barrier
+    const gptr<const T> P = as_global<T>(static_cast<const void*>(d.P));
+    for (int idx = tid; idx < NB * NB; idx += NTH) Ps[(idx / NB) * LDP + idx % NB] = P[idx];
+  }
   // Gram blocks owned by this wave and their accumulators.
   int gbi[MG], gbj[MG];
   d4 gacc[MG];
@@ -347,7 +359,10 @@ k_wide(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items) 
 #pragma unroll
             for (int kk = 0; kk < NK4; ++kk) {
               const double b = At[(4 * kk + (l >> 4)) * LDA + 16 * rb + (l & 15)];
-              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[0][kk], b, acc, 0, 0, 0);
+              double a;
+              if constexpr (PL) a = Ps[(16 * t + (l & 15)) * LDP + 4 * kk + (l >> 4)];
+              else a = pa[0][kk];
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
           }
           __syncthreads();  // every wave is past its reads of this step's rows
